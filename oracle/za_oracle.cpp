@@ -1,0 +1,882 @@
+/*
+ * WENO-ZA6 oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, deliberately unoptimised CPU implementation of what the
+ * MI355X path computes.  It exists so that the GPU library can be checked
+ * against something written straight from the paper (Gu, Wang, Don, Jung,
+ * "A Family of Even-Order Central-Upwind WENO Schemes with Averaged Downwind
+ * and Novel Global Smoothness Indicators", arXiv 2603.26272).  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may load it;
+ * the product path never does.  It shares no code, header, table or helper
+ * with the HIP library.
+ *
+ * Everything is templated on the arithmetic type:
+ *   double      -- the reference for FP64 parity,
+ *   float       -- the FP32-reconstruction reading (state and RK3 stay FP64),
+ *   __float128  -- the critical-point operator test (Section 3.1, tables
+ *                  tab:ncp0 / tab:ncp1 print errors below FP64 rounding),
+ *   Cnt         -- a counting scalar that tallies the algorithmic FLOPs.
+ *
+ * Build: g++ -O2 -ffp-contract=off -fPIC -shared -fopenmp  (see build.py).
+ * -ffp-contract=off keeps every product and sum separately rounded, so the
+ * results follow the written formulas operation by operation.
+ *
+ * Readings of the paper that are not stated in it (each listed in the design
+ * notes of the repository):
+ *   - weights are the non-affine-invariant Z type (mu = 1) unless the Ai flag
+ *     is set (Section 3 says WENO-ZA6 uses Z weights without the Ai property);
+ *   - Lax-Friedrichs speeds for systems are per characteristic field,
+ *     alpha_s = max |lambda_s| over the interior cells of the RHS input;
+ *   - the averaged state for the characteristic projection is Roe's average;
+ *   - 2D time step: dt = CFL / (max(|u|+c)/dx + max(|v|+c)/dy);
+ *   - initial data and the solution are point values at cell centres.
+ */
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <cstdlib>
+#include <vector>
+#include <algorithm>
+#include <quadmath.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef __float128 quad;
+
+/* ------------------------------------------------------------------------ */
+/* FLOP-counting scalar.                                                     */
+/* Every +,-,*,/,sqrt on data is counted once.  Operations a compiler folds   */
+/* away are not counted: both operands literal constants, a product with a    */
+/* literal 0 or +-1, or a sum with a literal 0.  |x|, max and comparisons are */
+/* tallied separately and are not FLOPs.                                      */
+/* ------------------------------------------------------------------------ */
+struct OpCount { long long add, mul, div, sqrt, other; };
+static OpCount g_ops;
+
+struct Cnt {
+  double v; bool lit;
+  Cnt() : v(0), lit(true) {}
+  Cnt(double x) : v(x), lit(true) {}           /* literal constant */
+  static Cnt data(double x) { Cnt c(x); c.lit = false; return c; }
+};
+static inline Cnt mk(double v, bool lit) { Cnt c(v); c.lit = lit; return c; }
+static inline bool is_lit(const Cnt& a, double x) { return a.lit && a.v == x; }
+static inline Cnt operator+(Cnt a, Cnt b) {
+  if (a.lit && b.lit) return mk(a.v + b.v, true);
+  if (is_lit(a, 0.0)) return b;
+  if (is_lit(b, 0.0)) return a;
+  g_ops.add++; return mk(a.v + b.v, false);
+}
+static inline Cnt operator-(Cnt a) { return mk(-a.v, a.lit); }
+static inline Cnt operator-(Cnt a, Cnt b) {
+  if (a.lit && b.lit) return mk(a.v - b.v, true);
+  if (is_lit(b, 0.0)) return a;
+  if (is_lit(a, 0.0)) return mk(-b.v, false);
+  g_ops.add++; return mk(a.v - b.v, false);
+}
+static inline Cnt operator*(Cnt a, Cnt b) {
+  if (a.lit && b.lit) return mk(a.v * b.v, true);
+  if (is_lit(a, 0.0) || is_lit(b, 0.0)) return mk(0.0, true);
+  if (is_lit(a, 1.0)) return b;
+  if (is_lit(b, 1.0)) return a;
+  if (is_lit(a, -1.0)) return mk(-b.v, false);
+  if (is_lit(b, -1.0)) return mk(-a.v, false);
+  g_ops.mul++; return mk(a.v * b.v, false);
+}
+static inline Cnt operator/(Cnt a, Cnt b) {
+  if (a.lit && b.lit) return mk(a.v / b.v, true);
+  if (is_lit(a, 0.0)) return mk(0.0, true);
+  if (is_lit(b, 1.0)) return a;
+  g_ops.div++; return mk(a.v / b.v, false);
+}
+static inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
+static inline bool operator<(Cnt a, Cnt b) { g_ops.other++; return a.v < b.v; }
+static inline bool operator>(Cnt a, Cnt b) { g_ops.other++; return a.v > b.v; }
+static inline bool operator<=(Cnt a, Cnt b) { g_ops.other++; return a.v <= b.v; }
+static inline bool operator!=(Cnt a, Cnt b) { return a.v != b.v; }
+
+/* ---- per-type elementary functions ---- */
+static inline double r_abs(double x) { return std::fabs(x); }
+static inline float  r_abs(float x)  { return std::fabs(x); }
+static inline quad   r_abs(quad x)   { return fabsq(x); }
+static inline Cnt    r_abs(Cnt x)    { g_ops.other++; return mk(std::fabs(x.v), x.lit); }
+static inline double r_sqrt(double x) { return std::sqrt(x); }
+static inline float  r_sqrt(float x)  { return std::sqrt(x); }
+static inline quad   r_sqrt(quad x)   { return sqrtq(x); }
+static inline Cnt    r_sqrt(Cnt x)    { if (!x.lit) g_ops.sqrt++; return mk(std::sqrt(x.v), x.lit); }
+static inline double r_pow(double x, double p) { return std::pow(x, p); }
+static inline float  r_pow(float x, float p)   { return std::pow(x, p); }
+static inline quad   r_pow(quad x, quad p)     { return powq(x, p); }
+static inline Cnt    r_pow(Cnt x, Cnt p)       { g_ops.other++; return mk(std::pow(x.v, p.v), false); }
+static inline double r_exp(double x) { return std::exp(x); }
+static inline quad   r_exp(quad x)   { return expq(x); }
+template <class R> static inline R r_max(R a, R b) { return (a < b) ? b : a; }
+
+template <class R> static inline R lit(double x) { return R(x); }
+template <class R> static inline R frac(int n, int d) { return R(n) / R(d); }
+/* state (double) -> arithmetic type */
+template <class R> static inline R from_state(double x) { return R(x); }
+template <> inline Cnt from_state<Cnt>(double x) { return Cnt::data(x); }
+template <class R> static inline double to_state(R x) { return (double)x; }
+template <> inline double to_state<Cnt>(Cnt x) { return x.v; }
+template <> inline double to_state<quad>(quad x) { return (double)x; }
+
+/* ------------------------------------------------------------------------ */
+/* O1: one split reconstruction at one interface (Section 2, Section 3).     */
+/* ------------------------------------------------------------------------ */
+struct ReconParams {
+  double p;        /* power parameter p of eq:weight_nonlinear (paper: 1) */
+  double eps;      /* sensitivity epsilon (paper: 1e-40 in FP64)          */
+  int ai;          /* 1: affine-invariant descaler mu[f] of eq:aimu       */
+  double mu0;      /* mu_0 of eq:aimu                                      */
+  int linear;      /* 1: omega = d (the linear sixth-order central flux)   */
+};
+
+/* Constants of the r = 3 scheme, built in the arithmetic type R so that the
+ * quad build carries them to quad accuracy.  Values as printed in Section 3:
+ * c6 (central flux), c_k (eq:subflux_S6_coeffs), d (ideal weights),
+ * c_tau (eq:GSI with r = 3). */
+template <class R> struct ZA6Const {
+  R c6[6];
+  R ck[4][3];
+  R d[4];
+  R ctau[6];
+  R half, thirteen_thirds, quarter;
+  ZA6Const() {
+    const int c6n[6] = {1, -8, 37, 37, -8, 1};
+    for (int j = 0; j < 6; ++j) c6[j] = frac<R>(c6n[j], 60);
+    const int ckn[4][3] = {{2, -7, 11}, {-1, 5, 2}, {2, 5, -1}, {11, -7, 2}};
+    for (int k = 0; k < 4; ++k)
+      for (int j = 0; j < 3; ++j) ck[k][j] = frac<R>(ckn[k][j], 6);
+    const int dn[4] = {1, 9, 9, 1};
+    for (int k = 0; k < 4; ++k) d[k] = frac<R>(dn[k], 20);
+    const int ctn[6] = {-1, 5, -10, 10, -5, 1};
+    for (int j = 0; j < 6; ++j) ctau[j] = R(ctn[j]);
+    half = frac<R>(1, 2);
+    thirteen_thirds = frac<R>(13, 3);
+    quarter = frac<R>(1, 4);
+  }
+};
+
+/* Intermediate values of one reconstruction, exported for the tests. */
+struct ReconDetail {
+  double q[4];      /* candidate fluxes q_0..q_3                        */
+  double beta[5];   /* beta_0, beta_1, beta_2, beta_d, beta_3 (average)  */
+  double tau;       /* global smoothness indicator                      */
+  double mu;        /* descaler (1 unless Ai)                           */
+  double omega[4];  /* nonlinear weights                                */
+};
+
+/* Reconstruct h at x_{i+1/2} from v[0..5] = (f_{i-2}, ..., f_{i+3}).
+ * For the negative split flux the caller passes the same six points in
+ * reversed order (mirror symmetry about x_{i+1/2}, Section 2).            */
+template <class R>
+static R recon_za6(const R v[6], const ZA6Const<R>& K, const ReconParams& P,
+                   ReconDetail* det) {
+  /* Candidate fluxes: q_k = <c_k, f_k> on S_k = {x_{i-2+k}, .., x_{i+k}}
+   * (eq:numerical_subflux with the coefficients eq:subflux_S6_coeffs). */
+  R q[4];
+  for (int k = 0; k < 4; ++k)
+    q[k] = K.ck[k][0] * v[k] + K.ck[k][1] * v[k + 1] + K.ck[k][2] * v[k + 2];
+
+  R out;
+  if (P.linear) {
+    /* omega = d: the convex combination collapses to the linear flux
+     * (eq:numerical_flux_FD_linear_comb). */
+    out = K.d[0] * q[0] + K.d[1] * q[1] + K.d[2] * q[2] + K.d[3] * q[3];
+    if (det) {
+      for (int k = 0; k < 4; ++k) { det->q[k] = to_state(q[k]); det->omega[k] = to_state(K.d[k]); }
+      for (int k = 0; k < 5; ++k) det->beta[k] = 0;
+      det->tau = 0; det->mu = 1;
+    }
+    return out;
+  }
+
+  /* Local smoothness indicators, eq:SI written out for r = 3.  With dx = 1
+   * and x_i = 0, the quadratic p_k on S_k (cells at offsets o, o+1, o+2,
+   * o = k-2) has p_k'' = 2 a_2 with a_2 = (f_o - 2 f_{o+1} + f_{o+2}) / 2
+   * and p_k'(0) = a_1 = (f_{o+1} - f_o) - (2o+1) a_2 (the cell averages of
+   * xi and xi^2 over [l-1/2, l+1/2] are l and l^2 + 1/12).  eq:SI then gives
+   * beta = a_1^2 + (13/3) a_2^2.  k = 3 is the downwind polynomial p_3, whose
+   * indicator beta_d is measured over I_i like the others. */
+  R beta[4];
+  for (int k = 0; k < 4; ++k) {
+    const int o = k - 2;
+    R a2 = K.half * (v[k] - lit<R>(2.0) * v[k + 1] + v[k + 2]);
+    R a1 = (v[k + 1] - v[k]) - lit<R>((double)(2 * o + 1)) * a2;
+    beta[k] = a1 * a1 + K.thirteen_thirds * (a2 * a2);
+  }
+  /* beta_3: arithmetic mean of beta_0, beta_1, beta_2 and beta_d
+   * (eq:SI_downwind with r = 3). */
+  R beta_d = beta[3];
+  R beta3 = K.quarter * (beta[0] + beta[1] + beta[2] + beta_d);
+  R b[4] = {beta[0], beta[1], beta[2], beta3};
+
+  /* Global smoothness indicator tau = <c_tau, f^6>^2 (eq:GSI). */
+  R t = R(0);
+  for (int j = 0; j < 6; ++j) t = t + K.ctau[j] * v[j];
+  R tau = t * t;
+
+  /* Descaler mu[f] (eq:aimu); mu = 1 for the non-Ai Z weights. */
+  R mu = R(1);
+  if (P.ai) {
+    R mean = R(0);
+    for (int j = 0; j < 6; ++j) mean = mean + v[j];
+    mean = mean / R(6);
+    R s = R(0);
+    for (int j = 0; j < 6; ++j) s = s + r_abs(v[j] - mean);
+    mu = s / R(6) + R(P.mu0);
+  }
+
+  /* Gamma_k (eq:weight_nonlinear), alpha_k = d_k (L + Gamma_k)^q with
+   * L = 1, q = 1 (eq:weights_unnormalized), omega_k (eq:weights_general). */
+  const R eps = R(P.eps);
+  const R epsmu2 = P.ai ? eps * (mu * mu) : eps;
+  R alpha[4], asum = R(0);
+  for (int k = 0; k < 4; ++k) {
+    R g = tau / (b[k] + epsmu2);
+    if (P.p != 1.0) g = r_pow(g, R(P.p));
+    alpha[k] = K.d[k] * (R(1) + g);
+    asum = asum + alpha[k];
+  }
+  R omega[4];
+  for (int k = 0; k < 4; ++k) omega[k] = alpha[k] / asum;
+
+  /* eq:numerical_flux_WENO */
+  out = omega[0] * q[0] + omega[1] * q[1] + omega[2] * q[2] + omega[3] * q[3];
+
+  if (det) {
+    for (int k = 0; k < 4; ++k) { det->q[k] = to_state(q[k]); det->omega[k] = to_state(omega[k]); }
+    det->beta[0] = to_state(beta[0]); det->beta[1] = to_state(beta[1]);
+    det->beta[2] = to_state(beta[2]); det->beta[3] = to_state(beta_d);
+    det->beta[4] = to_state(beta3);
+    det->tau = to_state(tau); det->mu = to_state(mu);
+  }
+  return out;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Problem description (the oracle's own; mirrors the library's fields).     */
+/* ------------------------------------------------------------------------ */
+enum { SYS_ADVECTION = 0, SYS_EULER = 1, SYS_BURGERS = 2, SYS_BUCKLEY = 3 };
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
+enum { DT_CFL = 0, DT_CFL_H2 = 1 };
+enum { LF_PER_FIELD = 0, LF_SCALAR = 1 };
+
+extern "C" {
+typedef struct {
+  int32_t dim, system, nx, ny;
+  double xlo, xhi, ylo, yhi;
+  int32_t bc_x, bc_y;
+  double gamma;
+  double adv_speed[2];
+  double cfl;
+  int32_t dt_rule;
+  int32_t recon_fp32;
+  double p, eps;
+  int32_t ai;
+  double mu0;
+  int32_t lf;
+  int32_t linear_weights;
+} orc_problem;
+}
+
+static int ncomp(const orc_problem& P) {
+  if (P.system == SYS_EULER) return P.dim == 1 ? 3 : 4;
+  return 1;
+}
+
+/* Ghost cells (three per side, the width of the six-point stencil):
+ * periodic wraps, transmissive copies the nearest interior cell. */
+static inline int bc_index(int j, int n, int bc) {
+  if (bc == BC_PERIODIC) { int r = j % n; return r < 0 ? r + n : r; }
+  return j < 0 ? 0 : (j >= n ? n - 1 : j);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Scalar flux functions (Section 2, Section 4.1).                            */
+/* ------------------------------------------------------------------------ */
+template <class R> static R scalar_flux(const orc_problem& P, int dir, R u) {
+  switch (P.system) {
+    case SYS_ADVECTION: return from_state<R>(P.adv_speed[dir]) * u;
+    case SYS_BURGERS: return R(0.5) * u * u;
+    default: { /* Buckley-Leverett, tab:scalar_fluxes */
+      R a = u * u, w = R(1) - u;
+      return a / (a + R(0.25) * (w * w));
+    }
+  }
+}
+static double scalar_dflux(const orc_problem& P, int dir, double u) {
+  switch (P.system) {
+    case SYS_ADVECTION: return P.adv_speed[dir];
+    case SYS_BURGERS: return u;
+    default: {
+      /* f = u^2 / D, D = u^2 + (1-u)^2/4,  f' = (2u D - u^2 D') / D^2 */
+      double D = u * u + 0.25 * (1 - u) * (1 - u);
+      double Dp = 2 * u - 0.5 * (1 - u);
+      return (2 * u * D - u * u * Dp) / (D * D);
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Euler: primitive variables, physical flux, wave speeds, eigenvectors.     */
+/* Fields (rho, rho u, [rho v], E); p = (gamma-1)(E - rho |u|^2 / 2).         */
+/* ------------------------------------------------------------------------ */
+template <class R>
+static void euler_flux(int m, int dir, R gm1, const R* Q, R* F) {
+  R rho = Q[0];
+  R u = Q[1] / rho;
+  if (m == 3) {
+    R p = gm1 * (Q[2] - R(0.5) * rho * u * u);
+    F[0] = Q[1];
+    F[1] = Q[1] * u + p;
+    F[2] = (Q[2] + p) * u;
+    return;
+  }
+  R v = Q[2] / rho;
+  R p = gm1 * (Q[3] - R(0.5) * rho * (u * u + v * v));
+  R un = dir == 0 ? u : v;
+  F[0] = rho * un;
+  F[1] = Q[1] * un + (dir == 0 ? p : R(0));
+  F[2] = Q[2] * un + (dir == 1 ? p : R(0));
+  F[3] = (Q[3] + p) * un;
+}
+
+/* Left/right eigenvectors of dF_dir/dQ at a state (u, v, H, c).  Columns of
+ * Rm are right eigenvectors for the eigenvalues (u_n - c, u_n, [u_n], u_n + c);
+ * Lm is the inverse (rows are left eigenvectors).  Textbook forms, written
+ * out separately for each direction. */
+template <class R>
+static void euler_eigen(int m, int dir, R gm1, R u, R v, R H, R c, R* Rm, R* Lm) {
+  const R q2 = m == 3 ? R(0.5) * (u * u) : R(0.5) * (u * u + v * v);
+  const R b1 = gm1 / (c * c);
+  const R b2 = b1 * q2;
+  const R ic = R(1) / c;
+  const R h = R(0.5);
+  if (m == 3) {
+    R Rv[9] = {R(1), R(1), R(1),
+               u - c, u, u + c,
+               H - u * c, q2, H + u * c};
+    R Lv[9] = {h * (b2 + u * ic), -h * (b1 * u + ic), h * b1,
+               R(1) - b2, b1 * u, -b1,
+               h * (b2 - u * ic), -h * (b1 * u - ic), h * b1};
+    for (int i = 0; i < 9; ++i) { Rm[i] = Rv[i]; Lm[i] = Lv[i]; }
+    return;
+  }
+  if (dir == 0) {
+    R Rv[16] = {R(1), R(1), R(0), R(1),
+                u - c, u, R(0), u + c,
+                v, v, R(1), v,
+                H - u * c, q2, v, H + u * c};
+    R Lv[16] = {h * (b2 + u * ic), -h * (b1 * u + ic), -h * (b1 * v), h * b1,
+                R(1) - b2, b1 * u, b1 * v, -b1,
+                -v, R(0), R(1), R(0),
+                h * (b2 - u * ic), -h * (b1 * u - ic), -h * (b1 * v), h * b1};
+    for (int i = 0; i < 16; ++i) { Rm[i] = Rv[i]; Lm[i] = Lv[i]; }
+  } else {
+    R Rv[16] = {R(1), R(0), R(1), R(1),
+                u, R(1), u, u,
+                v - c, R(0), v, v + c,
+                H - v * c, u, q2, H + v * c};
+    R Lv[16] = {h * (b2 + v * ic), -h * (b1 * u), -h * (b1 * v + ic), h * b1,
+                -u, R(1), R(0), R(0),
+                R(1) - b2, b1 * u, b1 * v, -b1,
+                h * (b2 - v * ic), -h * (b1 * u), -h * (b1 * v - ic), h * b1};
+    for (int i = 0; i < 16; ++i) { Rm[i] = Rv[i]; Lm[i] = Lv[i]; }
+  }
+}
+
+/* Wave speeds of one sweep direction over the interior cells, in FP64:
+ * alpha[s] = max |lambda_s| (s over the m characteristic fields) and
+ * smax = max(|u_n| + c).  Returns 0 if the state is finite and physical,
+ * 1 otherwise (rho <= 0, p <= 0 or a non-finite value). */
+static int wave_speeds(const orc_problem& P, const double* q, int dir, double* alpha, double* smax) {
+  const int m = ncomp(P);
+  const size_t ncell = (size_t)P.nx * P.ny;
+  int bad = 0;
+  for (int s = 0; s < 4; ++s) alpha[s] = 0;
+  *smax = 0;
+  if (P.system != SYS_EULER) {
+    double a = 0;
+    for (size_t i = 0; i < ncell; ++i) {
+      double u = q[i];
+      if (u != u) bad = 1;
+      a = std::max(a, std::fabs(scalar_dflux(P, dir, u)));
+    }
+    alpha[0] = a; *smax = a;
+    return bad;
+  }
+  const double gm1 = P.gamma - 1;
+  for (size_t i = 0; i < ncell; ++i) {
+    double Q[4];
+    for (int c = 0; c < m; ++c) Q[c] = q[c * ncell + i];
+    double rho = Q[0];
+    double u = Q[1] / rho, v = m == 4 ? Q[2] / rho : 0.0;
+    double E = Q[m - 1];
+    double p = gm1 * (E - 0.5 * rho * (u * u + v * v));
+    double c2 = P.gamma * p / rho;
+    if (!(rho > 0) || !(p > 0) || !(c2 > 0) || !std::isfinite(E) || !std::isfinite(Q[1])) { bad = 1; continue; }
+    double c = std::sqrt(c2);
+    double un = dir == 0 ? u : v;
+    alpha[0] = std::max(alpha[0], std::fabs(un - c));
+    alpha[1] = std::max(alpha[1], std::fabs(un));
+    alpha[m - 1] = std::max(alpha[m - 1], std::fabs(un + c));
+    *smax = std::max(*smax, std::fabs(un) + c);
+  }
+  if (m == 4) alpha[2] = alpha[1];
+  if (P.lf == LF_SCALAR) {
+    for (int s = 0; s < m; ++s) alpha[s] = *smax;
+  }
+  return bad;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O2/O3: numerical fluxes of one sweep.                                      */
+/* Interface k (0..n) of a line of n cells sits at x_{k-1/2}, between cells   */
+/* k-1 and k; its six-point stencil is cells k-3 .. k+2.                      */
+/* ------------------------------------------------------------------------ */
+template <class R>
+static void line_fluxes(const orc_problem& P, const ZA6Const<R>& K, const ReconParams& RP,
+                        int dir, const double* alpha, int n, int bc,
+                        /* gather cell j (ghosts allowed) of this line into Q[m] */
+                        const double* const* lineptr, size_t stride,
+                        double* Fhat /* [m][n+1], stride n+1 */) {
+  const int m = ncomp(P);
+  const R h = R(0.5);
+  /* physical flux of every cell including ghosts, f_j = f(Q_j) */
+  std::vector<R> Qc((size_t)(n + 6) * m), Fc((size_t)(n + 6) * m);
+  for (int j = -3; j < n + 3; ++j) {
+    int jj = bc_index(j, n, bc);
+    R* Qj = &Qc[(size_t)(j + 3) * m];
+    R* Fj = &Fc[(size_t)(j + 3) * m];
+    for (int c = 0; c < m; ++c) Qj[c] = from_state<R>(lineptr[c][(size_t)jj * stride]);
+    if (P.system == SYS_EULER) euler_flux<R>(m, dir, R(P.gamma - 1), Qj, Fj);
+    else Fj[0] = scalar_flux<R>(P, dir, Qj[0]);
+  }
+  for (int k = 0; k <= n; ++k) {
+    if (P.system != SYS_EULER) {
+      /* Global Lax-Friedrichs splitting f^(+-) = (f +- alpha Q)/2 (eq:LF),
+       * f^+ reconstructed from (f_{i-2..i+3}), f^- from the mirrored
+       * stencil (f_{i+3..i-2}); F = f^+ + f^-. */
+      R a = from_state<R>(alpha[0]);
+      R vp[6], vm[6];
+      for (int j = 0; j < 6; ++j) {
+        const int cj = k - 3 + j;
+        R Qj = Qc[(size_t)(cj + 3)], Fj = Fc[(size_t)(cj + 3)];
+        vp[j] = h * (Fj + a * Qj);
+        vm[5 - j] = h * (Fj - a * Qj);
+      }
+      R fh = recon_za6<R>(vp, K, RP, nullptr) + recon_za6<R>(vm, K, RP, nullptr);
+      Fhat[k] = to_state(fh);
+      continue;
+    }
+    /* Characteristic-wise LF splitting for the Euler system (Section 4.2):
+     * Roe average of cells k-1 and k, project the six-point stencil of Q and
+     * F onto the characteristic fields, split and reconstruct each field,
+     * project back. */
+    const R gm1 = R(P.gamma - 1);
+    const R* QL = &Qc[(size_t)(k - 1 + 3) * m];
+    const R* QR = &Qc[(size_t)(k + 3) * m];
+    R rl = QL[0], rr = QR[0];
+    R ul = QL[1] / rl, ur = QR[1] / rr;
+    R vl = m == 4 ? QL[2] / rl : R(0), vr = m == 4 ? QR[2] / rr : R(0);
+    R pl = gm1 * (QL[m - 1] - h * rl * (ul * ul + vl * vl));
+    R pr = gm1 * (QR[m - 1] - h * rr * (ur * ur + vr * vr));
+    R Hl = (QL[m - 1] + pl) / rl, Hr = (QR[m - 1] + pr) / rr;
+    R sl = r_sqrt(rl), sr = r_sqrt(rr);
+    R wl = sl / (sl + sr), wr = sr / (sl + sr);
+    R u = wl * ul + wr * ur;
+    R v = wl * vl + wr * vr;
+    R H = wl * Hl + wr * Hr;
+    R q2 = m == 4 ? h * (u * u + v * v) : h * (u * u);
+    R c2 = gm1 * (H - q2);
+    R c = r_sqrt(c2);
+    R Rm[16], Lm[16];
+    euler_eigen<R>(m, dir, gm1, u, v, H, c, Rm, Lm);
+    R W[6][4], G[6][4];
+    for (int j = 0; j < 6; ++j) {
+      const R* Qj = &Qc[(size_t)(k - 3 + j + 3) * m];
+      const R* Fj = &Fc[(size_t)(k - 3 + j + 3) * m];
+      for (int s = 0; s < m; ++s) {
+        R w = R(0), g = R(0);
+        for (int cc = 0; cc < m; ++cc) {
+          w = w + Lm[s * m + cc] * Qj[cc];
+          g = g + Lm[s * m + cc] * Fj[cc];
+        }
+        W[j][s] = w; G[j][s] = g;
+      }
+    }
+    R gh[4];
+    for (int s = 0; s < m; ++s) {
+      R a = from_state<R>(alpha[s]);
+      R vp[6], vm[6];
+      for (int j = 0; j < 6; ++j) {
+        vp[j] = h * (G[j][s] + a * W[j][s]);
+        vm[5 - j] = h * (G[j][s] - a * W[j][s]);
+      }
+      gh[s] = recon_za6<R>(vp, K, RP, nullptr) + recon_za6<R>(vm, K, RP, nullptr);
+    }
+    for (int cc = 0; cc < m; ++cc) {
+      R f = R(0);
+      for (int s = 0; s < m; ++s) f = f + Rm[cc * m + s] * gh[s];
+      Fhat[(size_t)cc * (n + 1) + k] = to_state(f);
+    }
+  }
+}
+
+struct Ctx {
+  orc_problem P;
+  ReconParams RP;
+  int m;
+  double dx, dy;
+  size_t ncell;
+};
+
+static int make_ctx(const orc_problem* p, Ctx* C) {
+  if (!p) return 1;
+  C->P = *p;
+  if (p->dim != 1 && p->dim != 2) return 1;
+  if (p->nx < 1 || p->ny < 1 || (p->dim == 1 && p->ny != 1)) return 1;
+  C->m = ncomp(*p);
+  C->RP.p = p->p; C->RP.eps = p->eps; C->RP.ai = p->ai; C->RP.mu0 = p->mu0;
+  C->RP.linear = p->linear_weights;
+  C->dx = (p->xhi - p->xlo) / p->nx;
+  C->dy = p->dim == 2 ? (p->yhi - p->ylo) / p->ny : 1.0;
+  C->ncell = (size_t)p->nx * p->ny;
+  return 0;
+}
+
+/* All numerical fluxes of one direction for state q: fx [m][ny][nx+1] or
+ * fy [m][ny+1][nx].  alpha from this RHS's own input. */
+template <class R>
+static int sweep_fluxes(const Ctx& C, const double* q, int dir, const double* alpha, double* F) {
+  const orc_problem& P = C.P;
+  const int m = C.m;
+  const int nx = P.nx, ny = P.ny;
+  static const ZA6Const<R> K;
+  if (dir == 0) {
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y) {
+      const double* lp[4];
+      for (int c = 0; c < m; ++c) lp[c] = q + c * C.ncell + (size_t)y * nx;
+      std::vector<double> Fl((size_t)m * (nx + 1));
+      line_fluxes<R>(P, K, C.RP, 0, alpha, nx, P.bc_x, lp, 1, Fl.data());
+      for (int c = 0; c < m; ++c)
+        for (int k = 0; k <= nx; ++k)
+          F[(size_t)c * ny * (nx + 1) + (size_t)y * (nx + 1) + k] = Fl[(size_t)c * (nx + 1) + k];
+    }
+  } else {
+#pragma omp parallel for schedule(static)
+    for (int x = 0; x < nx; ++x) {
+      const double* lp[4];
+      for (int c = 0; c < m; ++c) lp[c] = q + c * C.ncell + x;
+      std::vector<double> Fl((size_t)m * (ny + 1));
+      line_fluxes<R>(P, K, C.RP, 1, alpha, ny, P.bc_y, lp, (size_t)nx, Fl.data());
+      for (int c = 0; c < m; ++c)
+        for (int k = 0; k <= ny; ++k)
+          F[(size_t)c * (ny + 1) * nx + (size_t)k * nx + x] = Fl[(size_t)c * (ny + 1) + k];
+    }
+  }
+  return 0;
+}
+
+/* L(Q) = -(F_{i+1/2} - F_{i-1/2})/dx  [+ the same in y]   (eq:hyperbolic_1D_scalar_h,
+ * dimension by dimension in 2D, Section 4.3). */
+template <class R>
+static int rhs_impl(const Ctx& C, const double* q, double* rhs) {
+  const orc_problem& P = C.P;
+  const int m = C.m, nx = P.nx, ny = P.ny;
+  double ax[4], ay[4], sx, sy;
+  int bad = wave_speeds(P, q, 0, ax, &sx);
+  std::vector<double> fx((size_t)m * ny * (nx + 1));
+  sweep_fluxes<R>(C, q, 0, ax, fx.data());
+  for (int c = 0; c < m; ++c)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const double* f = &fx[(size_t)c * ny * (nx + 1) + (size_t)y * (nx + 1)];
+        rhs[(size_t)c * C.ncell + (size_t)y * nx + x] = -(f[x + 1] - f[x]) / C.dx;
+      }
+  if (P.dim == 2) {
+    bad |= wave_speeds(P, q, 1, ay, &sy);
+    std::vector<double> fy((size_t)m * (ny + 1) * nx);
+    sweep_fluxes<R>(C, q, 1, ay, fy.data());
+    for (int c = 0; c < m; ++c)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const double* f = &fy[(size_t)c * (ny + 1) * nx];
+          rhs[(size_t)c * C.ncell + (size_t)y * nx + x] += -(f[(size_t)(y + 1) * nx + x] - f[(size_t)y * nx + x]) / C.dy;
+        }
+  }
+  return bad;
+}
+
+static int rhs_any(const Ctx& C, const double* q, double* rhs) {
+  return C.P.recon_fp32 ? rhs_impl<float>(C, q, rhs) : rhs_impl<double>(C, q, rhs);
+}
+
+/* CFL time step from the current state (Section 4, reading for 2D). */
+static double cfl_dt(const Ctx& C, const double* q, int* bad) {
+  const orc_problem& P = C.P;
+  if (P.dt_rule == DT_CFL_H2) {
+    double h = P.dim == 2 ? std::min(C.dx, C.dy) : C.dx;
+    return P.cfl * h * h;
+  }
+  double a[4], sx, sy = 0;
+  *bad |= wave_speeds(P, q, 0, a, &sx);
+  if (P.dim == 1) return P.cfl * C.dx / sx;
+  *bad |= wave_speeds(P, q, 1, a, &sy);
+  return P.cfl / (sx / C.dx + sy / C.dy);
+}
+
+/* One SSP-RK3 step in Shu-Osher form:
+ *   Q1 = Qn + dt L(Qn)
+ *   Q2 = 3/4 Qn + 1/4 (Q1 + dt L(Q1))
+ *   Qn+1 = 1/3 Qn + 2/3 (Q2 + dt L(Q2))                                     */
+static int rk3_step(const Ctx& C, double* q, double dt) {
+  const size_t n = (size_t)C.m * C.ncell;
+  std::vector<double> L(n), q1(n), q2(n);
+  int bad = rhs_any(C, q, L.data());
+  for (size_t i = 0; i < n; ++i) q1[i] = q[i] + dt * L[i];
+  bad |= rhs_any(C, q1.data(), L.data());
+  for (size_t i = 0; i < n; ++i) q2[i] = 0.75 * q[i] + 0.25 * (q1[i] + dt * L[i]);
+  bad |= rhs_any(C, q2.data(), L.data());
+  for (size_t i = 0; i < n; ++i) q[i] = (1.0 / 3.0) * q[i] + (2.0 / 3.0) * (q2[i] + dt * L[i]);
+  for (size_t i = 0; i < n; ++i) if (!std::isfinite(q[i])) bad = 1;
+  return bad;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 3.1 critical-point operator test: f(x) = x^(ncp+1) e^(0.75 x) on   */
+/* nodes x_j = -1 + j dx, j = 0..2/dx; D_j = (h_{j+1/2} - h_{j-1/2})/dx with  */
+/* the positive reconstruction; error = max_j |D_j - f'(x_j)|.                */
+/* ------------------------------------------------------------------------ */
+template <class R>
+static double critical_point_test(int ncp, int inv_dx, double p, int eps_mode, double eps, int ai, double mu0) {
+  static const ZA6Const<R> K;
+  const int n = 2 * inv_dx;              /* nodes 0..n */
+  const R dx = R(2) / R(n);
+  ReconParams RP;
+  RP.p = p; RP.ai = ai; RP.mu0 = mu0; RP.linear = 0;
+  if (eps_mode == 1) {
+    /* epsilon = dx^(2(ncp-1)) (tab:ncp1, ncp = 4, 5) */
+    R e = R(1);
+    for (int i = 0; i < 2 * (ncp - 1); ++i) e = e * dx;
+    RP.eps = (double)e;
+    /* keep the quad value exact enough: eps only enters as beta + eps */
+  } else {
+    RP.eps = eps;
+  }
+  auto f = [&](R x) { R r = R(1); for (int i = 0; i < ncp + 1; ++i) r = r * x; return r * r_exp(R(0.75) * x); };
+  auto fp = [&](R x) {
+    R xn = R(1); for (int i = 0; i < ncp; ++i) xn = xn * x;   /* x^ncp */
+    return (R(ncp + 1) * xn + R(0.75) * xn * x) * r_exp(R(0.75) * x);
+  };
+  /* interfaces j+1/2 for j = -1 .. n need nodes j-2 .. j+3, i.e. -3 .. n+3 */
+  std::vector<R> fv((size_t)n + 7);
+  for (int j = -3; j <= n + 3; ++j) fv[(size_t)(j + 3)] = f(R(-1) + R(j) * dx);
+  std::vector<R> fh((size_t)n + 2);
+  for (int j = -1; j <= n; ++j) {
+    R v[6];
+    for (int t = 0; t < 6; ++t) v[t] = fv[(size_t)(j - 2 + t + 3)];
+    fh[(size_t)(j + 1)] = recon_za6<R>(v, K, RP, nullptr);
+  }
+  R err = R(0);
+  for (int j = 0; j <= n; ++j) {
+    R D = (fh[(size_t)(j + 1)] - fh[(size_t)j]) / dx;
+    R e = r_abs(D - fp(R(-1) + R(j) * dx));
+    if (err < e) err = e;
+  }
+  return (double)err;
+}
+
+/* ------------------------------------------------------------------------ */
+/* C ABI of the oracle (loaded by the test-suite through ctypes).            */
+/* ------------------------------------------------------------------------ */
+extern "C" {
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+int orc_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* O1 in FP64 on v[0..5]; detail (15 doubles: q[4], beta[5], tau, mu,
+ * omega[4]) may be NULL. */
+double orc_recon(const double* v6, double p, double eps, int ai, double mu0, int linear, double* detail) {
+  static const ZA6Const<double> K;
+  ReconParams RP{p, eps, ai, mu0, linear};
+  ReconDetail d;
+  double r = recon_za6<double>(v6, K, RP, detail ? &d : nullptr);
+  if (detail) std::memcpy(detail, &d, sizeof(d));
+  return r;
+}
+/* O1 in FP32 (inputs rounded to float first). */
+double orc_recon_f32(const double* v6, double p, double eps, int ai, double mu0, int linear) {
+  static const ZA6Const<float> K;
+  ReconParams RP{p, eps, ai, mu0, linear};
+  float v[6];
+  for (int j = 0; j < 6; ++j) v[j] = (float)v6[j];
+  return (double)recon_za6<float>(v, K, RP, nullptr);
+}
+/* O1 in quad precision; the six inputs are given as decimal strings so that
+ * the test can supply values beyond FP64 resolution. */
+double orc_recon_q(const char* const* v6, double p, double eps, int ai, double mu0, char* out, int outlen) {
+  static const ZA6Const<quad> K;
+  ReconParams RP{p, eps, ai, mu0, 0};
+  quad v[6];
+  for (int j = 0; j < 6; ++j) v[j] = strtoflt128(v6[j], nullptr);
+  quad r = recon_za6<quad>(v, K, RP, nullptr);
+  if (out) quadmath_snprintf(out, (size_t)outlen, "%.36Qe", r);
+  return (double)r;
+}
+
+double orc_critical_point_test(int ncp, int inv_dx, double p, int eps_mode, double eps, int ai, double mu0, int use_quad) {
+  if (use_quad) return critical_point_test<quad>(ncp, inv_dx, p, eps_mode, eps, ai, mu0);
+  return critical_point_test<double>(ncp, inv_dx, p, eps_mode, eps, ai, mu0);
+}
+
+/* Eigenvector matrices used by the characteristic projection (row-major
+ * m x m), exported so the tests can check L R = I and L A R = diag(lambda). */
+void orc_euler_eigen(int m, int dir, double gamma, double u, double v, double H, double c,
+                     double* Rm, double* Lm) {
+  euler_eigen<double>(m, dir, gamma - 1, u, v, H, c, Rm, Lm);
+}
+
+int orc_ncomp(const orc_problem* p) { return ncomp(*p); }
+
+int orc_wave_speeds(const orc_problem* p, const double* q, double* alpha /*[2][4]*/, double* smax /*[2]*/) {
+  Ctx C; if (make_ctx(p, &C)) return 1;
+  int bad = wave_speeds(C.P, q, 0, alpha, &smax[0]);
+  if (C.P.dim == 2) bad |= wave_speeds(C.P, q, 1, alpha + 4, &smax[1]);
+  else { for (int s = 0; s < 4; ++s) alpha[4 + s] = 0; smax[1] = 0; }
+  return bad ? 4 : 0;
+}
+
+/* Interface fluxes: fx [m][ny][nx+1]; fy [m][ny+1][nx] (2D only, may be NULL). */
+int orc_fluxes(const orc_problem* p, const double* q, double* fx, double* fy) {
+  Ctx C; if (make_ctx(p, &C)) return 1;
+  double a[4], s;
+  int bad = wave_speeds(C.P, q, 0, a, &s);
+  if (C.P.recon_fp32) sweep_fluxes<float>(C, q, 0, a, fx); else sweep_fluxes<double>(C, q, 0, a, fx);
+  if (C.P.dim == 2 && fy) {
+    bad |= wave_speeds(C.P, q, 1, a, &s);
+    if (C.P.recon_fp32) sweep_fluxes<float>(C, q, 1, a, fy); else sweep_fluxes<double>(C, q, 1, a, fy);
+  }
+  return bad ? 4 : 0;
+}
+
+int orc_rhs(const orc_problem* p, const double* q, double* rhs) {
+  Ctx C; if (make_ctx(p, &C)) return 1;
+  return rhs_any(C, q, rhs) ? 4 : 0;
+}
+
+double orc_cfl_dt(const orc_problem* p, const double* q) {
+  Ctx C; if (make_ctx(p, &C)) return -1;
+  int bad = 0;
+  return cfl_dt(C, q, &bad);
+}
+
+/* One RK3 step; dt <= 0 takes the CFL step. */
+int orc_step(const orc_problem* p, double* q, double dt, double* dt_used) {
+  Ctx C; if (make_ctx(p, &C)) return 1;
+  int bad = 0;
+  if (!(dt > 0)) dt = cfl_dt(C, q, &bad);
+  if (dt_used) *dt_used = dt;
+  bad |= rk3_step(C, q, dt);
+  return bad ? 4 : 0;
+}
+
+/* Integrate to t_final.  Fixed-step rule (CFL*h^2): n = ceil(T/dt (1-1e-12))
+ * steps, the last one T - (n-1) dt.  CFL rule: recompute dt each step from
+ * the current state and clip the last step to T.  t_final <= 0 runs exactly
+ * max_steps CFL steps without clipping.  max_steps > 0 caps the count. */
+int orc_solve(const orc_problem* p, double* q, double t_final, int64_t max_steps,
+              int64_t* steps_out, double* t_out) {
+  Ctx C; if (make_ctx(p, &C)) return 1;
+  int bad = 0;
+  int64_t steps = 0;
+  double t = 0;
+  if (t_final > 0 && C.P.dt_rule == DT_CFL_H2) {
+    double dt = cfl_dt(C, q, &bad);
+    int64_t n = (int64_t)std::ceil(t_final / dt * (1 - 1e-12));
+    for (int64_t s = 0; s < n; ++s) {
+      if (max_steps > 0 && steps >= max_steps) break;
+      double h = (s == n - 1) ? t_final - (double)(n - 1) * dt : dt;
+      bad |= rk3_step(C, q, h);
+      t = (s == n - 1) ? t_final : t + h;
+      ++steps;
+      if (bad) break;
+    }
+  } else if (t_final > 0) {
+    while (t < t_final) {
+      if (max_steps > 0 && steps >= max_steps) break;
+      double dt = cfl_dt(C, q, &bad);
+      if (bad) break;
+      bool last = false;
+      if (t + dt >= t_final) { dt = t_final - t; last = true; }
+      bad |= rk3_step(C, q, dt);
+      t = last ? t_final : t + dt;
+      ++steps;
+      if (bad) break;
+    }
+  } else {
+    for (int64_t s = 0; s < max_steps; ++s) {
+      double dt = cfl_dt(C, q, &bad);
+      if (bad) break;
+      bad |= rk3_step(C, q, dt);
+      t += dt;
+      ++steps;
+      if (bad) break;
+    }
+  }
+  if (steps_out) *steps_out = steps;
+  if (t_out) *t_out = t;
+  return bad ? 4 : 0;
+}
+
+/* Algorithmic operation counts of one RHS evaluation (both sweeps in 2D),
+ * via the counting scalar.  counts[0..4] = add/sub, mul, div, sqrt, other
+ * (abs/max/compare/pow).  Returns the number of interface reconstructions
+ * (interfaces over all sweeps), or -1 on error.  Per-cell work (physical
+ * flux) and the interface work are included; the wave-speed reduction, the
+ * flux difference and the RK3 combination are FP64 and counted separately
+ * by the caller from their closed forms. */
+int64_t orc_count_ops(const orc_problem* p, const double* q, int64_t* counts) {
+  Ctx C; if (make_ctx(p, &C)) return -1;
+#ifdef _OPENMP
+  int saved = omp_get_max_threads();
+  omp_set_num_threads(1);
+#endif
+  const orc_problem& P = C.P;
+  double ax[4], ay[4], s;
+  wave_speeds(P, q, 0, ax, &s);
+  std::memset(&g_ops, 0, sizeof(g_ops));
+  std::vector<double> fx((size_t)C.m * P.ny * (P.nx + 1));
+  sweep_fluxes<Cnt>(C, q, 0, ax, fx.data());
+  int64_t nir = (int64_t)(P.nx + 1) * P.ny;
+  if (P.dim == 2) {
+    wave_speeds(P, q, 1, ay, &s);
+    std::vector<double> fy((size_t)C.m * (P.ny + 1) * P.nx);
+    sweep_fluxes<Cnt>(C, q, 1, ay, fy.data());
+    nir += (int64_t)P.nx * (P.ny + 1);
+  }
+  counts[0] = g_ops.add; counts[1] = g_ops.mul; counts[2] = g_ops.div;
+  counts[3] = g_ops.sqrt; counts[4] = g_ops.other;
+#ifdef _OPENMP
+  omp_set_num_threads(saved);
+#endif
+  return nir;
+}
+
+} /* extern "C" */

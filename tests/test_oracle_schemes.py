@@ -1,0 +1,294 @@
+"""Pins of the oracle's full right-hand side and time stepping against things
+the paper and the mathematics fix: a Fourier closed form for the linear
+scheme, sixth-order convergence on smooth data, exact Riemann solutions,
+exact preservation of constant states, discrete conservation, symmetries,
+the eigen-decomposition of the Euler Jacobian, and the paper's step count
+for its 2D Riemann configuration 3 (Section 4.4 timing table)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2603_26272_amd import workloads as W
+from paper_2603_26272_amd.problem import (ADVECTION, DT_CFL, DT_CFL_H2, EULER, PERIODIC,
+                                          TRANSMISSIVE, Problem)
+from tests.riemann_exact import sample as riemann_sample
+
+C6 = np.array([1, -8, 37, 37, -8, 1]) / 60.0
+
+
+def closed_form_error(N, T=2.0):
+    """Linear six-point central flux + SSP-RK3 on u0 = sin(pi x), periodic
+    [-1, 1], dt = 0.5 dx^2: the mode e^{i pi x} is multiplied per step by
+    G(z) = 1 + z + z^2/2 + z^3/6, z = dt lambda, with lambda the symbol of
+    -(F_{j+1/2} - F_{j-1/2})/dx for F_{j+1/2} = <c6, u_{j-2..j+3}>.
+    Evaluated in 40-digit arithmetic (G^n with n up to 1.6e5)."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    dx = 2.0 / N
+    dt = 0.5 * dx * dx                      # the FP64 step the solver takes
+    n = math.ceil(T / dt * (1 - 1e-12))
+    last = T - (n - 1) * dt
+    dxm = mp.mpf(2) / N
+    th = mp.pi * dxm
+    c6 = [mp.mpf(c) / 60 for c in (1, -8, 37, 37, -8, 1)]
+    S = sum(c6[m] * mp.expj(th * (m - 2)) for m in range(6))
+    lam = -(1 - mp.expj(-th)) * S / dxm
+    G = lambda z: 1 + z + z * z / 2 + z ** 3 / 6
+    amp = G(mp.mpf(dt) * lam) ** (n - 1) * G(mp.mpf(last) * lam)
+    x = W.centres(N, -1.0, 1.0)
+    e = np.array([abs(float(mp.im(amp * mp.expj(mp.pi * mp.mpf(xi)))) - math.sin(math.pi * (xi - T)))
+                  for xi in x])
+    return e.max(), e.mean()
+
+
+@pytest.mark.parametrize("N", [25, 50, 100])
+def test_linear_mode_matches_closed_form(orc, N):
+    P, q0 = W.advection_sine(N)
+    q, steps, t, st = orc.solve(P.with_(linear_weights=1), q0, 2.0)
+    assert st == 0 and abs(t - 2.0) < 1e-14
+    x = W.centres(N, -1.0, 1.0)
+    e = np.abs(q[0, 0] - np.sin(math.pi * (x - 2.0)))
+    linf, l1 = closed_form_error(N)
+    # equal up to accumulated rounding (about steps * 1e-18 here)
+    assert abs(e.max() - linf) <= 1e-6 * linf + 1e-13
+    assert abs(e.mean() - l1) <= 1e-6 * l1 + 1e-13
+
+
+def test_closed_form_values():
+    """The closed-form errors themselves (C0 expected table)."""
+    expect = {25: (1.12e-5, 7.12e-6), 50: (1.76e-7, 1.12e-7), 100: (2.76e-9, 1.76e-9),
+              200: (4.31e-11, 2.75e-11), 400: (6.73e-13, 4.29e-13)}
+    for N, (li, l1) in expect.items():
+        a, b = closed_form_error(N)
+        assert abs(a - li) <= 0.006 * li and abs(b - l1) <= 0.006 * l1, (N, a, b)
+
+
+def test_za6_sixth_order_on_smooth_advection(orc):
+    """Nonlinear WENO-ZA6 on sin(pi x): within 1% of the linear scheme's
+    closed-form error and sixth order (omega - d = O(dx^4) away from
+    critical points, Section 3.1)."""
+    errs = []
+    for N in (25, 50, 100):
+        P, q0 = W.advection_sine(N)
+        q, steps, t, st = orc.solve(P, q0, 2.0)
+        assert st == 0
+        x = W.centres(N, -1.0, 1.0)
+        e = np.abs(q[0, 0] - np.sin(math.pi * (x - 2.0))).max()
+        linf, _ = closed_form_error(N)
+        assert abs(e - linf) <= 0.01 * linf, (N, e, linf)
+        errs.append(e)
+    for a, b in zip(errs, errs[1:]):
+        assert 5.8 <= math.log2(a / b) <= 6.2
+
+
+def test_entropy_wave_sixth_order(orc):
+    """Smooth 1D Euler density wave (u = 1, p = 1): sixth-order L1/Linf."""
+    T = 0.2
+    errs = []
+    for N in (20, 40, 80):
+        P, q0 = W.entropy_wave_1d(N)
+        q, steps, t, st = orc.solve(P, q0, T)
+        assert st == 0
+        x = W.centres(N, 0.0, 1.0)
+        e = np.abs(q[0, 0] - (1 + 0.2 * np.sin(2 * math.pi * (x - T))))
+        errs.append((e.max(), e.mean()))
+    for (a, a1), (b, b1) in zip(errs, errs[1:]):
+        assert math.log2(a / b) > 5.6 and math.log2(a1 / b1) > 5.6, errs
+
+
+@pytest.mark.parametrize("name", ["sod", "lax", "123"])
+def test_shock_tubes_converge_to_exact_solution(orc, name):
+    """Shock tubes of the paper's 1D Riemann table against the exact Riemann
+    solution: the density L1 error falls under refinement and is small."""
+    errs = []
+    for N in (100, 200, 400):
+        P, q0, T = W.shock_tube(name, N)
+        q, steps, t, st = orc.solve(P, q0, T)
+        assert st == 0 and abs(t - T) < 1e-12
+        (rl, ul, pl), (rr, ur, pr), _ = W.SHOCK_TUBES[name]
+        x = W.centres(N, -5.0, 5.0)
+        ex = riemann_sample((rl, ul, pl), (rr, ur, pr), x, T)
+        errs.append(np.abs(q[0, 0] - ex[0]).mean() * 10.0)   # L1 over [-5, 5]
+    assert errs[0] > errs[1] > errs[2], errs
+    assert errs[1] < {"sod": 0.03, "lax": 0.08, "123": 0.08}[name], errs
+
+
+def _uniform(P, prim):
+    rho, u, v, p = prim
+    if P.dim == 1:
+        return np.ascontiguousarray(W.conservative(np.full(P.nx, rho), u, v, p, dim=1).reshape(3, 1, P.nx))
+    return np.ascontiguousarray(W.conservative(np.full((P.ny, P.nx), rho), u, v, p, dim=2))
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_constant_state_and_free_stream_exact(orc, fp32):
+    """Sum c_k = 1 and sum d = 1: a uniform flow has identical fluxes at every
+    interface, so L(Q) is exactly zero (bitwise), in 1D and 2D, for both BCs."""
+    cases = [Problem(dim=1, nx=37, bc_x=TRANSMISSIVE), Problem(dim=1, nx=37, bc_x=PERIODIC),
+             Problem(dim=2, nx=19, ny=23, bc_x=PERIODIC, bc_y=TRANSMISSIVE),
+             Problem(dim=2, nx=19, ny=23, bc_x=TRANSMISSIVE, bc_y=PERIODIC)]
+    for P in cases:
+        P = P.fp32() if fp32 else P
+        for prim in [(1.3, 0.0, 0.0, 0.7), (0.4, -0.9, 0.35, 2.1)]:
+            q = _uniform(P, prim)
+            L, st = orc.rhs(P, q)
+            assert st == 0 and np.all(L == 0.0), (P, prim, np.abs(L).max())
+    P = Problem(dim=1, system=ADVECTION, nx=31, bc_x=PERIODIC)
+    L, st = orc.rhs(P, np.full((1, 1, 31), 0.3))
+    assert np.all(L == 0.0)
+
+
+def test_periodic_conservation(orc):
+    """Telescoping of -(F_{i+1/2} - F_{i-1/2})/dx: with periodic boundaries
+    the sum of L over all cells vanishes to rounding."""
+    P, q = W.quadrants_2d(3, 32)
+    P = P.with_(bc_x=PERIODIC, bc_y=PERIODIC)
+    L, st = orc.rhs(P, q)
+    fx, fy, _ = orc.fluxes(P, q)
+    scale = max(np.abs(fx).max(), np.abs(fy).max())
+    for c in range(4):
+        assert abs(L[c].sum()) * P.dx <= 64 * 32 * 32 * 2.3e-16 * scale * 2
+    # periodic flux arrays: first and last interface coincide bitwise
+    assert np.array_equal(fx[:, :, 0], fx[:, :, -1])
+    assert np.array_equal(fy[:, 0, :], fy[:, -1, :])
+
+
+def test_conservation_over_run(orc):
+    P, q = W.quadrants_2d(5, 24)
+    P = P.with_(bc_x=PERIODIC, bc_y=PERIODIC)
+    tot0 = q.reshape(4, -1).sum(axis=1)
+    q1, steps, t, st = orc.solve(P, q, 0.0, max_steps=10)
+    assert st == 0 and steps == 10
+    tot1 = q1.reshape(4, -1).sum(axis=1)
+    assert np.all(np.abs(tot1 - tot0) <= 1e-12 * np.abs(q).reshape(4, -1).sum(axis=1))
+
+
+def test_mirror_symmetry_1d(orc):
+    """x -> -x with u -> -u maps the solution onto its mirror image."""
+    P, q = W.riemann_1d(4, 256)
+    qm = q[:, :, ::-1].copy()
+    qm[1] *= -1
+    a, *_ = orc.solve(P, q, 0.0, max_steps=20)
+    b, *_ = orc.solve(P, qm, 0.0, max_steps=20)
+    b = b[:, :, ::-1].copy()
+    b[1] *= -1
+    assert np.allclose(a, b, rtol=0, atol=1e-12 * np.abs(a).max())
+
+
+def test_transpose_symmetry_2d(orc):
+    """x <-> y with u <-> v maps the 2D solution onto its transpose."""
+    P, q = W.quadrants_2d(1, 40)
+    qt = np.ascontiguousarray(np.stack([q[0].T, q[2].T, q[1].T, q[3].T]))
+    a, *_ = orc.solve(P, q, 0.0, max_steps=5)
+    b, *_ = orc.solve(P, qt, 0.0, max_steps=5)
+    bt = np.stack([b[0].T, b[2].T, b[1].T, b[3].T])
+    assert np.allclose(a, bt, rtol=0, atol=1e-12 * np.abs(a).max())
+
+
+def test_affine_invariance_flag(orc):
+    """eq:aimu: with the Ai descaler the weights are unchanged by
+    f -> lambda f + c, so the flux maps to lambda F + c; small-amplitude jumps
+    keep their adaptivity.  Without it (mu = 1) a jump of amplitude 1e-22
+    falls below epsilon and the weights collapse to the linear ones."""
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        v = rng.normal(size=6)
+        _, d0 = orc.recon(v, ai=1, detail=True)
+        for lam, c in [(2.0, 3.0), (1e-22, 0.0), (1e5, -7.0)]:
+            r, d1 = orc.recon(lam * v + c, ai=1, detail=True)
+            assert np.allclose(d1["omega"], d0["omega"], rtol=1e-9, atol=1e-12)
+    step = np.array([0, 0, 0, 1.0, 1.0, 1.0]) * 1e-22
+    _, dn = orc.recon(step, ai=0, detail=True)
+    _, da = orc.recon(step, ai=1, detail=True)
+    d = np.array([1, 9, 9, 1]) / 20
+    assert np.allclose(dn["omega"], d, rtol=1e-6)
+    assert da["omega"][3] < 1e-3 and da["omega"][2] < 1e-3
+
+
+def _euler_flux(Q, direction, g=1.4):
+    if len(Q) == 3:
+        rho, mx, E = Q
+        u = mx / rho
+        p = (g - 1) * (E - 0.5 * rho * u * u)
+        return np.array([mx, mx * u + p, (E + p) * u])
+    rho, mx, my, E = Q
+    u, v = mx / rho, my / rho
+    p = (g - 1) * (E - 0.5 * rho * (u * u + v * v))
+    un = u if direction == 0 else v
+    return np.array([rho * un, mx * un + (p if direction == 0 else 0), my * un + (p if direction == 1 else 0),
+                     (E + p) * un])
+
+
+@pytest.mark.parametrize("m,direction", [(3, 0), (4, 0), (4, 1)])
+def test_eigenvectors_diagonalise_jacobian(orc, m, direction):
+    """L R = I and L A R = diag(lambda) with A = dF/dQ by complex-step
+    differentiation of the physical flux."""
+    g = 1.4
+    rng = np.random.default_rng(m + direction)
+    for _ in range(10):
+        rho, u, v, p = rng.uniform(0.2, 2), rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0.2, 2)
+        if m == 3:
+            v = 0.0
+            Q = np.array([rho, rho * u, p / (g - 1) + 0.5 * rho * u * u], dtype=complex)
+        else:
+            Q = np.array([rho, rho * u, rho * v, p / (g - 1) + 0.5 * rho * (u * u + v * v)], dtype=complex)
+        A = np.zeros((m, m))
+        h = 1e-30
+        for j in range(m):
+            dq = Q.copy()
+            dq[j] += 1j * h
+            A[:, j] = np.imag(_euler_flux(dq, direction, g)) / h
+        c = math.sqrt(g * p / rho)
+        H = (Q[-1].real + p) / rho
+        Rm, Lm = orc.euler_eigen(m, direction, g, u, v, H, c)
+        assert np.allclose(Lm @ Rm, np.eye(m), atol=1e-13)
+        un = u if direction == 0 else v
+        lam = [un - c, un, un + c] if m == 3 else [un - c, un, un, un + c]
+        assert np.allclose(Lm @ A @ Rm, np.diag(lam), atol=1e-12)
+
+
+def test_wave_speeds_per_field(orc):
+    P, q = W.quadrants_2d(2, 16)
+    a, s, st = orc.wave_speeds(P, q)
+    rho = q[0]
+    u, v = q[1] / rho, q[2] / rho
+    p = 0.4 * (q[3] - 0.5 * rho * (u * u + v * v))
+    c = np.sqrt(1.4 * p / rho)
+    close = lambda x, y: abs(x - y) <= 1e-15 * abs(y)
+    assert close(a[0][0], np.abs(u - c).max()) and close(a[0][3], np.abs(u + c).max())
+    assert a[0][1] == a[0][2] and close(a[0][1], np.abs(u).max())
+    assert close(a[1][0], np.abs(v - c).max()) and close(a[1][3], np.abs(v + c).max())
+    assert abs(s[0] - (np.abs(u) + c).max()) <= 1e-15 * s[0]
+
+
+def test_nonphysical_state_flagged(orc):
+    P, q = W.riemann_1d(0, 64)
+    q = q.copy()
+    q[0, 0, 10] = -1.0
+    _, st = orc.rhs(P, q)
+    assert st == 4
+    q[0, 0, 10] = float("nan")
+    _, st = orc.rhs(P, q)
+    assert st == 4
+
+
+@pytest.mark.slow
+def test_config3_step_count_pins_2d_dt_rule(orc):
+    """Section 4.4: WENO-ZA6 takes 3497 RK steps for configuration 3 at 400^2,
+    T = 0.8, CFL 0.45.  The count grows like n^k with k slightly above 1 (the
+    peak wave speeds sharpen with resolution): fit k from 50^2 and 100^2 and
+    extrapolate to 400^2.  The summed 2D rule
+    dt = CFL / (max(|u|+c)/dx + max(|v|+c)/dy) lands within 3% of 3497; a rule
+    dt = CFL dx / max(|u|+c, |v|+c) would need about half as many steps."""
+    orc.set_threads(8)
+    counts = {}
+    for n in (50, 100):
+        P, q0, T = W.riemann_config3(n)
+        q, steps, t, st = orc.solve(P, q0, T)
+        assert st == 0 and abs(t - T) < 1e-12
+        counts[n] = steps
+    k = math.log2(counts[100] / counts[50])
+    assert 1.0 < k < 1.15, counts
+    pred = counts[100] * 4.0 ** k
+    assert abs(pred - 3497) <= 0.03 * 3497, (counts, pred)
