@@ -1,0 +1,184 @@
+/*
+ * za.h -- C ABI of libza, the MI355X (gfx950) WENO-ZA6 solver library.
+ *
+ * The calls follow the paper's statement of the problem (Gu, Wang, Don, Jung,
+ * arXiv 2603.26272): a hyperbolic conservation law Q_t + div F(Q) = 0 on a
+ * uniform mesh (Section 2, eq:hyperbolic_1D_scalar and the 2D Euler system of
+ * Section 4.3), discretised by the conservative finite-difference form
+ * dQ_i/dt = -(F_{i+1/2} - F_{i-1/2})/dx (eq:hyperbolic_1D_scalar_h) with
+ * WENO-ZA6 interface fluxes (Sections 2-3) and integrated by third-order
+ * SSP (TVD) Runge-Kutta (Section 4, opening paragraph).
+ *
+ * Conventions shared by every call:
+ *  - No exception crosses the ABI; every call returns a za_status.
+ *  - State buffers are DEVICE pointers (HIP/PyTorch allocations on the
+ *    context's device).  Layout is structure-of-arrays, row-major with x
+ *    fastest: q[c][y][x], c < m, of point values at the cell centres
+ *    x_i = xlo + (i + 1/2) dx.  m = 1 (scalar), 3 (1D Euler: rho, rho u, E)
+ *    or 4 (2D Euler: rho, rho u, rho v, E).  The caller owns every buffer it
+ *    passes; the library never frees it and keeps no reference after the
+ *    enqueued work completes.
+ *  - All work is enqueued on the context's HIP stream.  za_rhs, za_rhs_fluxes
+ *    and za_step (with dt_used == NULL) are asynchronous; za_solve and
+ *    za_step with dt_used != NULL synchronise the stream before returning.
+ *  - Argument errors are detected before anything is enqueued and change no
+ *    state (ZA_ERR_ARG).  Device errors surface as ZA_ERR_DEVICE at the next
+ *    synchronising call.  A non-finite or non-physical state (rho <= 0,
+ *    p <= 0) seen by a wave-speed reduction yields ZA_ERR_NONFINITE at the
+ *    next synchronising call, with za_solve_info.nonfinite_step set.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef ZA_H
+#define ZA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ZA_OK = 0,
+  ZA_ERR_ARG = 1,          /* invalid argument; nothing was enqueued        */
+  ZA_ERR_NOMEM = 2,        /* device allocation failed / over HBM budget    */
+  ZA_ERR_DEVICE = 3,       /* a HIP call failed                              */
+  ZA_ERR_NONFINITE = 4,    /* NaN/Inf or rho <= 0 / p <= 0 met               */
+  ZA_ERR_UNSUPPORTED = 5,  /* valid but not implemented combination          */
+  ZA_ERR_BUSY = 6          /* server queue full                              */
+} za_status;
+
+/* Flux function.  ZA_ADVECTION: f = a u (Section 2); ZA_EULER: the Euler
+ * equations of gas dynamics (Sections 4.2, 4.3); ZA_BURGERS: f = u^2/2 and
+ * ZA_BUCKLEY: f = u^2/(u^2 + (1-u)^2/4) (Section 4.1, tab:scalar_fluxes). */
+typedef enum { ZA_ADVECTION = 0, ZA_EULER = 1, ZA_BURGERS = 2, ZA_BUCKLEY = 3 } za_system;
+typedef enum { ZA_BC_PERIODIC = 0, ZA_BC_TRANSMISSIVE = 1 } za_bc;
+/* ZA_FP32_RECON: flux splitting, characteristic projection, smoothness
+ * indicators and weights in FP32; the state, the flux difference and the
+ * RK3 stage accumulation stay FP64. */
+typedef enum { ZA_FP64 = 0, ZA_FP32_RECON = 1 } za_precision;
+/* ZA_DT_CFL: 1D dt = cfl dx / max(|u|+c); 2D dt = cfl / (max(|u|+c)/dx +
+ * max(|v|+c)/dy) (scalar laws: |f'(u)| in place of |u|+c).
+ * ZA_DT_CFL_H2: dt = cfl h^2 with h = min(dx, dy), fixed for the run. */
+typedef enum { ZA_DT_CFL = 0, ZA_DT_CFL_H2 = 1 } za_dt_rule;
+/* Lax-Friedrichs speed of eq:LF for systems: per characteristic field,
+ * alpha_s = max |lambda_s| over the grid, or one max(|u_n|+c) for all. */
+typedef enum { ZA_LF_PER_FIELD = 0, ZA_LF_SCALAR = 1 } za_lf;
+
+typedef struct {
+  int32_t dim;             /* 1 or 2                                         */
+  int32_t system;          /* za_system                                      */
+  int32_t nx, ny;          /* cells; ny = 1 when dim == 1                    */
+  double  xlo, xhi, ylo, yhi;
+  int32_t bc_x, bc_y;      /* za_bc; three ghost cells per side             */
+  double  gamma;           /* ratio of specific heats (1.4 in the paper)     */
+  double  adv_speed[2];    /* advection velocity (ZA_ADVECTION)              */
+  double  cfl;             /* CFL number (0.45 in the paper)                 */
+  int32_t dt_rule;         /* za_dt_rule                                     */
+  int32_t precision;       /* za_precision                                   */
+  double  p;               /* power parameter of eq:weight_nonlinear (1)     */
+  double  eps;             /* sensitivity epsilon (1e-40 FP64, 1e-20 FP32)   */
+  int32_t affine_invariant;/* 0: mu = 1 (Section 3); 1: mu[f] of eq:aimu      */
+  double  mu0;             /* mu_0 of eq:aimu (1e-40 FP64, 1e-8 FP32)        */
+  int32_t lf;              /* za_lf                                          */
+  int32_t linear_weights;  /* 1: omega = d (the linear central flux), tests  */
+} za_problem;
+
+typedef struct za_ctx za_ctx;
+
+typedef struct {
+  int64_t steps;           /* RK3 steps taken                                 */
+  double  t;               /* final simulated time                            */
+  double  dt_min, dt_max;  /* extreme step sizes used                         */
+  int64_t nonfinite_step;  /* first step whose input was non-finite, else -1  */
+} za_solve_info;
+
+/* Create a context for one problem shape on the current HIP device.
+ * hip_stream: a hipStream_t (NULL = the default stream).  Allocates the
+ * workspace (two RK3 stage states, the x-sweep partial RHS in 2D, the
+ * reduction partials and a device control block).  *out receives the
+ * context; on error *out is NULL. */
+za_status za_ctx_create(const za_problem* problem, void* hip_stream, za_ctx** out);
+za_status za_ctx_destroy(za_ctx* ctx);
+/* Rebind the stream used by later calls. */
+za_status za_ctx_set_stream(za_ctx* ctx, void* hip_stream);
+/* Number of doubles in one state: m * nx * ny. */
+size_t    za_state_count(const za_problem* problem);
+/* Device bytes the context allocates for this problem (admission control). */
+size_t    za_workspace_bytes(const za_problem* problem);
+
+/* rhs = L(q) = -(F_{i+1/2} - F_{i-1/2})/dx [- (G_{j+1/2} - G_{j-1/2})/dy]
+ * (eq:hyperbolic_1D_scalar_h, dimension by dimension in 2D), with the
+ * Lax-Friedrichs speeds taken from q itself.  q and rhs: device, m*nx*ny
+ * doubles, must not overlap. */
+za_status za_rhs(za_ctx* ctx, const double* q, double* rhs);
+
+/* The WENO-ZA6 numerical fluxes themselves (parity checks): fx[c][y][k] is
+ * F at x_{k-1/2}, k = 0..nx (size m*ny*(nx+1)); fy[c][k][x] is G at
+ * y_{k-1/2}, k = 0..ny (size m*(ny+1)*nx; 2D only, may be NULL). */
+za_status za_rhs_fluxes(za_ctx* ctx, const double* q, double* fx, double* fy);
+
+/* One SSP-RK3 step in place (Shu-Osher form).  dt > 0: that step; dt <= 0:
+ * the CFL step of the problem's dt rule from q.  dt_used (host, may be NULL):
+ * if given, the call synchronises and stores the dt taken. */
+za_status za_step(za_ctx* ctx, double* q, double dt, double* dt_used);
+
+/* Integrate q in place.  t_final > 0: to t_final, the last step clipped to
+ * land on it (ZA_DT_CFL_H2: n = ceil(T/dt (1 - 1e-12)) equal steps, the
+ * last T - (n-1) dt), stopping early after max_steps if max_steps > 0.
+ * t_final <= 0: exactly max_steps CFL steps without clipping.  dt and t stay
+ * on the device; the host checks progress once per captured chunk of steps.
+ * info (host, may be NULL) receives the step statistics.  Synchronises. */
+za_status za_solve(za_ctx* ctx, double* q, double t_final, int64_t max_steps, za_solve_info* info);
+
+/* FP64 totals of each conserved variable (fixed-order tree, so repeatable
+ * bit for bit): sums[c] = sum over cells of q[c].  sums: host, m doubles.
+ * Synchronises. */
+za_status za_conserved_sums(za_ctx* ctx, const double* q, double* sums);
+
+const char* za_status_str(za_status s);
+const char* za_ctx_last_error(const za_ctx* ctx);
+/* Per-launch device time (ms) of the most recent za_rhs/za_step/za_solve
+ * kernels, by kernel class, when timing is enabled (see za_ctx_set_timing):
+ * out[0] = x-sweep, out[1] = y-sweep(+stage), out[2] = wave-speed reduction;
+ * counts[k] = number of launches averaged. */
+za_status za_ctx_set_timing(za_ctx* ctx, int32_t enable);
+za_status za_ctx_kernel_times(za_ctx* ctx, double* avg_ms, int64_t* counts);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of independent solve requests.             */
+/* Requests are admitted while their device footprint fits the HBM budget */
+/* and a slot is free; every scheduler step advances all admitted requests */
+/* by one RK3 step with batched launches (one launch per kernel class for  */
+/* all slots, dispatched through a device slot table), retires finished    */
+/* requests and admits waiting ones.  The server owns a scheduler thread.  */
+/* ---------------------------------------------------------------------- */
+typedef struct za_server za_server;
+typedef int64_t za_req_id;
+
+typedef struct {
+  int64_t arrival_ns, admit_ns, finish_ns;   /* host monotonic clock        */
+  int64_t steps, interfaces;                 /* RK3 steps, IR computed      */
+  int32_t status;                            /* za_status of the request    */
+} za_req_stats;
+
+/* hbm_budget_bytes: cap on the summed footprint of admitted requests.
+ * max_slots: concurrent requests.  device: HIP device ordinal. */
+za_status za_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t device, za_server** out);
+/* Copies q0_host (m*nx*ny doubles) and queues the request for n_steps CFL
+ * steps.  ZA_ERR_NOMEM if its footprint exceeds the whole budget. */
+za_status za_server_submit(za_server* s, const za_problem* problem, const double* q0_host,
+                           int64_t n_steps, za_req_id* id);
+/* done = 1 once finished; then q_out_host (may be NULL) receives the final
+ * state and stats (may be NULL) the request's record.  The request is
+ * released after a successful poll with done = 1 and q_out_host != NULL. */
+za_status za_server_poll(za_server* s, za_req_id id, int32_t* done, double* q_out_host,
+                         za_req_stats* stats);
+/* Block until every submitted request has finished. */
+za_status za_server_drain(za_server* s);
+za_status za_server_destroy(za_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZA_H */

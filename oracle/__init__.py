@@ -69,6 +69,8 @@ def lib():
         L.orc_wave_speeds.argtypes = [PP, _DP, _DP, _DP]
         L.orc_fluxes.restype = C.c_int
         L.orc_fluxes.argtypes = [PP, _DP, _DP, _DP]
+        L.orc_fluxes_lines.restype = C.c_int
+        L.orc_fluxes_lines.argtypes = [PP, _DP, C.c_int, C.POINTER(C.c_int), C.c_int, _DP]
         L.orc_rhs.restype = C.c_int
         L.orc_rhs.argtypes = [PP, _DP, _DP]
         L.orc_cfl_dt.restype = C.c_double
@@ -191,6 +193,20 @@ def fluxes(pb, q):
     fy = np.zeros((m, P.ny + 1, P.nx)) if P.dim == 2 else None
     st = lib().orc_fluxes(C.byref(P), _ptr(q), _ptr(fx), _ptr(fy) if fy is not None else None)
     return fx, fy, st
+
+
+def fluxes_lines(pb, q, direction, lines):
+    """Fluxes of selected rows (direction 0, [l][m][nx+1]) or columns
+    (direction 1, [l][m][ny+1]) with the global LF speeds of q."""
+    P = _problem(pb)
+    q = _state(pb, q)
+    m = lib().orc_ncomp(C.byref(P))
+    n = P.nx if direction == 0 else P.ny
+    ln = np.ascontiguousarray(lines, dtype=np.int32)
+    out = np.zeros((len(ln), m, n + 1))
+    st = lib().orc_fluxes_lines(C.byref(P), _ptr(q), int(direction),
+                                ln.ctypes.data_as(C.POINTER(C.c_int)), len(ln), _ptr(out))
+    return out, st
 
 
 def rhs(pb, q):

@@ -776,6 +776,35 @@ int orc_fluxes(const orc_problem* p, const double* q, double* fx, double* fy) {
   return bad ? 4 : 0;
 }
 
+/* Fluxes of selected lines only (spot checks at full size): dir 0 gives the
+ * x-interface fluxes of rows lines[0..nl-1] as out[l][m][nx+1]; dir 1 the
+ * y-interface fluxes of columns lines[..] as out[l][m][ny+1].  The LF speeds
+ * are the global ones of q, exactly as in orc_fluxes. */
+int orc_fluxes_lines(const orc_problem* p, const double* q, int dir, const int* lines, int nl, double* out) {
+  Ctx C; if (make_ctx(p, &C)) return 1;
+  const orc_problem& P = C.P;
+  double a[4], s;
+  int bad = wave_speeds(P, q, dir, a, &s);
+  const int n = dir == 0 ? P.nx : P.ny;
+  const int m = C.m;
+#pragma omp parallel for schedule(dynamic)
+  for (int l = 0; l < nl; ++l) {
+    const double* lp[4];
+    for (int c = 0; c < m; ++c)
+      lp[c] = dir == 0 ? q + c * C.ncell + (size_t)lines[l] * P.nx : q + c * C.ncell + lines[l];
+    const size_t stride = dir == 0 ? 1 : (size_t)P.nx;
+    double* o = out + (size_t)l * m * (n + 1);
+    if (P.recon_fp32) {
+      static const ZA6Const<float> K;
+      line_fluxes<float>(P, K, C.RP, dir, a, n, dir == 0 ? P.bc_x : P.bc_y, lp, stride, o);
+    } else {
+      static const ZA6Const<double> K;
+      line_fluxes<double>(P, K, C.RP, dir, a, n, dir == 0 ? P.bc_x : P.bc_y, lp, stride, o);
+    }
+  }
+  return bad ? 4 : 0;
+}
+
 int orc_rhs(const orc_problem* p, const double* q, double* rhs) {
   Ctx C; if (make_ctx(p, &C)) return 1;
   return rhs_any(C, q, rhs) ? 4 : 0;

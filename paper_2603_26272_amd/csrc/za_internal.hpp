@@ -1,0 +1,32 @@
+// Library-internal context layout (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "za.h"
+#include "za_kernels.hpp"
+
+struct za_ctx {
+  za_problem prob;
+  int m = 1;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  za::Geom geom;
+  za::Phys ph;
+  double* q1 = nullptr;      // RK3 stage 1 state
+  double* q2 = nullptr;      // RK3 stage 2 state
+  double* lx = nullptr;      // 2D: x-sweep partial RHS
+  double* part = nullptr;    // reduction partials
+  za::DevCtl* ctl = nullptr; // device control block
+  int red_blocks = 1;
+  int chunk_steps = 0;       // steps per host check in za_solve (0: default)
+  bool timing = false;
+  hipEvent_t ev_open[3] = {nullptr, nullptr, nullptr};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events[3];
+  std::string err;
+};
+
+za_status za_validate(const za_problem* p, std::string* why);

@@ -1,0 +1,402 @@
+// Kernels of the WENO-ZA6 hot path for gfx950: sweeps, wave-speed
+// reductions, RK3 stage updates.
+#pragma once
+#include "za_device.hpp"
+
+namespace za {
+
+enum Sys { SYS_ADV = 0, SYS_EULER = 1, SYS_BURGERS = 2, SYS_BUCKLEY = 3 };
+enum Mode {
+  MODE_FLUX = 0,    // write the interface fluxes
+  MODE_RHS = 1,     // write (x) / accumulate (y) L
+  MODE_LX = 2,      // 2D stage, x-sweep: write L_x to workspace
+  MODE_STAGE = 3    // last sweep of a stage: L (+ L_x) -> RK3 stage update
+};
+
+// Device control block: Lax-Friedrichs speeds of the current stage input,
+// the step's dt, and the bookkeeping of a time integration.  Stays on the
+// device so that whole RK3 steps run without host round trips.
+struct DevCtl {
+  double alpha[2][4];     // per direction, per characteristic field
+  double smax[2];         // max(|u_n| + c) per direction
+  double dt;              // dt of the step in progress
+  double t;               // simulated time
+  double t_final;         // clip target (infinity: no clipping)
+  double dt_fixed;        // > 0: use this dt instead of the CFL rule
+  double dt_min, dt_max;
+  long long steps;        // completed steps
+  long long max_steps;    // stop after this many (<= 0: no cap)
+  long long bad_step;     // first step with a non-finite input, else -1
+  int active;             // 1 while stepping
+  int bad;                // non-finite / non-physical state seen
+  int last;               // the step in progress lands on t_final
+  int pad;
+};
+
+struct Geom {
+  int nx, ny;
+  int bc_x, bc_y;         // 0 periodic, 1 transmissive
+  double inv_dx, inv_dy;
+  double dx, dy;
+};
+
+struct Phys {
+  double gm1;             // gamma - 1
+  double gamma;
+  double adv[2];          // advection velocity
+  double cfl;
+  int dt_rule;            // 0 CFL, 1 CFL h^2
+  int lf_scalar;          // 1: one LF speed for every field
+};
+
+// Ghost cells: periodic wrap or transmissive clamp (three per side).
+__device__ __forceinline__ int bc_map(int j, int n, int bc) {
+  if (bc == 0) {
+    j = j < 0 ? j + n : j;
+    j = j >= n ? j - n : j;
+    // n >= 3 is required for a single wrap; smaller periodic grids use mod
+    if (j < 0 || j >= n) { j %= n; if (j < 0) j += n; }
+    return j;
+  }
+  return j < 0 ? 0 : (j >= n ? n - 1 : j);
+}
+
+// ---------------------------------------------------------------------------
+// Scalar flux functions and their derivatives (Section 2; Section 4.1).
+// ---------------------------------------------------------------------------
+template <int SYS, class T>
+__device__ __forceinline__ T scalar_f(T u, T a) {
+  if (SYS == SYS_ADV) return a * u;
+  if (SYS == SYS_BURGERS) return T(0.5) * u * u;
+  T s = u * u, w = T(1) - u;
+  return s / (s + T(0.25) * (w * w));
+}
+template <int SYS>
+__device__ __forceinline__ double scalar_df(double u, double a) {
+  if (SYS == SYS_ADV) return a;
+  if (SYS == SYS_BURGERS) return u;
+  double D = u * u + 0.25 * (1 - u) * (1 - u);
+  double Dp = 2 * u - 0.5 * (1 - u);
+  return (2 * u * D - u * u * Dp) / (D * D);
+}
+
+// ---------------------------------------------------------------------------
+// Interface flux of one sweep.  `base` points at component 0 of the line,
+// `cs` is the component stride (nx*ny), `ls` the stride along the line, n the
+// line length, k the interface (left face of cell k), bc the boundary rule.
+// DIR 1 permutes the 2D Euler state into the sweep-normal frame.
+// ---------------------------------------------------------------------------
+template <int SYS, int M, int DIR, class T, bool GP>
+__device__ __forceinline__ void iface_flux(const double* __restrict__ base, size_t cs, size_t ls, int n,
+                                           int k, int bc, const Phys& ph, const DevCtl* ctl,
+                                           const WeightCfg<T>& cfg, T (&Fh)[M]) {
+  if (SYS == SYS_EULER) {
+    double qs[6][M];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const size_t off = (size_t)bc_map(k - 3 + j, n, bc) * ls;
+      if (M == 4 && DIR == 1) {
+        qs[j][0] = base[off];
+        qs[j][1] = base[off + 2 * cs];
+        qs[j][2] = base[off + cs];
+        qs[j][3] = base[off + 3 * cs];
+      } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) qs[j][c] = base[off + c * cs];
+      }
+    }
+    T al[M];
+    if (M == 4) {
+      al[0] = (T)ctl->alpha[DIR][0]; al[1] = (T)ctl->alpha[DIR][1];
+      al[2] = (T)ctl->alpha[DIR][2]; al[3] = (T)ctl->alpha[DIR][3];
+    } else {
+      al[0] = (T)ctl->alpha[0][0]; al[1] = (T)ctl->alpha[0][1]; al[M - 1] = (T)ctl->alpha[0][3];
+    }
+    T F[M];
+    euler_flux<T, M, GP>(qs, (T)ph.gm1, al, cfg, F);
+    if (M == 4 && DIR == 1) {
+      Fh[0] = F[0]; Fh[1] = F[2]; Fh[2] = F[1]; Fh[3] = F[3];
+    } else {
+#pragma unroll
+      for (int c = 0; c < M; ++c) Fh[c] = F[c];
+    }
+  } else {
+    T w[6], g[6];
+    const T a = (T)ph.adv[DIR];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      w[j] = (T)base[(size_t)bc_map(k - 3 + j, n, bc) * ls];
+      g[j] = scalar_f<SYS, T>(w[j], a);
+    }
+    Fh[0] = split_pair<T, GP>(w, g, (T)ctl->alpha[DIR][0], cfg);
+  }
+}
+
+struct SweepArgs {
+  const double* q;       // sweep input Q^(s)
+  const double* qn;      // Q^n (stage update)
+  const double* lx;      // L_x (2D stage / rhs accumulate)
+  double* out;           // L, L_x, Q^(s+1) or fluxes
+  DevCtl* ctl;
+  Geom g;
+  Phys ph;
+  double ca, cb;         // stage: out = ca*qn + cb*(q + dt*L)
+  int check_active;      // stepping: skip when the integration is inactive
+};
+
+template <class T>
+struct CfgArg { WeightCfg<T> w; };
+
+// ---------------------------------------------------------------------------
+// x-sweep: one wavefront per line segment of 64 interfaces / 63 cells; each
+// lane computes one interface flux from its six-point stencil (coalesced,
+// shifted loads), the fluxes meet in LDS for the conservative difference.
+// Used for the 2D x-direction and for every 1D problem.
+// ---------------------------------------------------------------------------
+constexpr int XS_CELLS = 63;
+
+template <int SYS, int M, class T, int MODE, bool GP>
+__global__ __launch_bounds__(256) void k_sweep_x(SweepArgs a, CfgArg<T> cfg) {
+  if (a.check_active && !a.ctl->active) return;
+  __shared__ double fl[4][M][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nx = a.g.nx, ny = a.g.ny;
+  const int nseg = (nx + XS_CELLS - 1) / XS_CELLS;
+  const long long wid = (long long)blockIdx.x * 4 + wv;
+  const int line = (int)(wid / nseg), seg = (int)(wid % nseg);
+  const bool live = line < ny;
+  const int c0 = seg * XS_CELLS;
+  const int k = c0 + lane;
+  const size_t cs = (size_t)nx * ny;
+  const size_t row = (size_t)line * nx;
+  if (live && k <= nx) {
+    T F[M];
+    iface_flux<SYS, M, 0, T, GP>(a.q + row, cs, 1, nx, k, a.g.bc_x, a.ph, a.ctl, cfg.w, F);
+    if (MODE == MODE_FLUX) {
+      if (lane < XS_CELLS || k == nx) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) a.out[(size_t)c * ny * (nx + 1) + (size_t)line * (nx + 1) + k] = (double)F[c];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < M; ++c) fl[wv][c][lane] = (double)F[c];
+    }
+  }
+  if (MODE == MODE_FLUX) return;
+  __syncthreads();
+  const int i = c0 + lane;
+  if (!live || lane >= XS_CELLS || i >= nx) return;
+  const size_t idx = row + i;
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    const double L = -(fl[wv][c][lane + 1] - fl[wv][c][lane]) * a.g.inv_dx;
+    const size_t o = c * cs + idx;
+    if (MODE == MODE_RHS || MODE == MODE_LX) {
+      a.out[o] = L;
+    } else {  // MODE_STAGE (1D)
+      a.out[o] = a.ca * a.qn[o] + a.cb * (a.q[o] + a.ctl->dt * L);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y-sweep (2D): lanes run along x (coalesced), each wavefront marches down a
+// run of YS_CELLS cells, keeping the previous interface flux in registers for
+// the conservative difference.  MODE_STAGE adds L_x and applies the stage.
+// ---------------------------------------------------------------------------
+constexpr int YS_CELLS = 16;
+
+template <int SYS, int M, class T, int MODE, bool GP>
+__global__ __launch_bounds__(256) void k_sweep_y(SweepArgs a, CfgArg<T> cfg) {
+  if (a.check_active && !a.ctl->active) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nx = a.g.nx, ny = a.g.ny;
+  const int x = blockIdx.x * 64 + lane;
+  const int y0 = (blockIdx.y * 4 + wv) * YS_CELLS;
+  if (x >= nx || y0 >= ny) return;
+  const int y1 = min(y0 + YS_CELLS, ny);
+  const size_t cs = (size_t)nx * ny;
+  const double* colq = a.q + x;
+  T prev[M];
+  for (int k = y0; k <= y1; ++k) {
+    T F[M];
+    iface_flux<SYS, M, 1, T, GP>(colq, cs, (size_t)nx, ny, k, a.g.bc_y, a.ph, a.ctl, cfg.w, F);
+    if (MODE == MODE_FLUX) {
+      if (k < y1 || k == ny) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) a.out[(size_t)c * (ny + 1) * nx + (size_t)k * nx + x] = (double)F[c];
+      }
+    } else if (k > y0) {
+      const size_t idx = (size_t)(k - 1) * nx + x;
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const double L = -((double)F[c] - (double)prev[c]) * a.g.inv_dy;
+        const size_t o = c * cs + idx;
+        if (MODE == MODE_RHS) {
+          a.out[o] = a.lx[o] + L;
+        } else {  // MODE_STAGE
+          const double Lt = a.lx[o] + L;
+          a.out[o] = a.ca * a.qn[o] + a.cb * (a.q[o] + a.ctl->dt * Lt);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) prev[c] = F[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wave speeds: per block maxima of |u_n - c|, |u_n|, |u_n + c| per direction,
+// max(|u_n| + c) per direction, and a non-finite / non-physical flag.
+// Maxima are exact and order independent, so the result is deterministic.
+// part[b][0..9]: ax0 ax1 ax3 ay0 ay1 ay3 sx sy bad
+// ---------------------------------------------------------------------------
+constexpr int NPART = 9;
+constexpr int RED_BLOCKS_MAX = 1024;
+
+__device__ __forceinline__ double wave_max(double a, double b) { return a > b ? a : b; }
+
+template <int SYS, int M>
+__global__ __launch_bounds__(256) void k_wave_partial(const double* __restrict__ q, size_t ncell, Phys ph,
+                                                      const DevCtl* ctl, int check_active,
+                                                      double* __restrict__ part) {
+  if (check_active && !ctl->active) return;
+  double r[NPART];
+#pragma unroll
+  for (int i = 0; i < NPART; ++i) r[i] = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += (size_t)gridDim.x * blockDim.x) {
+    if (SYS == SYS_EULER) {
+      const double rho = q[i];
+      const double mx = q[ncell + i];
+      const double my = M == 4 ? q[2 * ncell + i] : 0.0;
+      const double E = q[(M - 1) * ncell + i];
+      const double u = mx / rho, v = my / rho;
+      const double p = ph.gm1 * (E - 0.5 * rho * (u * u + v * v));
+      const double c2 = ph.gamma * p / rho;
+      const bool ok = rho > 0.0 && p > 0.0 && c2 > 0.0 && (E - E) == 0.0 && (mx - mx) == 0.0 && (my - my) == 0.0;
+      if (!ok) { r[8] = 1.0; continue; }
+      const double c = sqrt(c2);
+      r[0] = wave_max(r[0], fabs(u - c));
+      r[1] = wave_max(r[1], fabs(u));
+      r[2] = wave_max(r[2], fabs(u + c));
+      r[3] = wave_max(r[3], fabs(v - c));
+      r[4] = wave_max(r[4], fabs(v));
+      r[5] = wave_max(r[5], fabs(v + c));
+      r[6] = wave_max(r[6], fabs(u) + c);
+      r[7] = wave_max(r[7], fabs(v) + c);
+    } else {
+      const double u = q[i];
+      if (!((u - u) == 0.0)) { r[8] = 1.0; continue; }
+      const double ax = fabs(scalar_df<SYS>(u, ph.adv[0]));
+      const double ay = fabs(scalar_df<SYS>(u, ph.adv[1]));
+      r[0] = wave_max(r[0], ax); r[6] = r[0];
+      r[3] = wave_max(r[3], ay); r[7] = r[3];
+    }
+  }
+  // wavefront then block reduction
+#pragma unroll
+  for (int i = 0; i < NPART; ++i) {
+    for (int off = 32; off > 0; off >>= 1) r[i] = wave_max(r[i], __shfl_xor(r[i], off, 64));
+  }
+  __shared__ double sm[4][NPART];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NPART; ++i) sm[wv][i] = r[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < NPART) {
+    double v = sm[0][threadIdx.x];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = wave_max(v, sm[w][threadIdx.x]);
+    part[(size_t)blockIdx.x * NPART + threadIdx.x] = v;
+  }
+}
+
+enum FinalKind { FIN_RHS = 0, FIN_STAGE0 = 1, FIN_STAGEK = 2 };
+
+template <int M>
+__global__ __launch_bounds__(64) void k_wave_final(const double* __restrict__ part, int nblk, DevCtl* ctl,
+                                                   Geom g, Phys ph, int dim, int kind, int is_euler) {
+  double r[NPART];
+#pragma unroll
+  for (int i = 0; i < NPART; ++i) r[i] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) {
+#pragma unroll
+    for (int i = 0; i < NPART; ++i) r[i] = wave_max(r[i], part[(size_t)b * NPART + i]);
+  }
+#pragma unroll
+  for (int i = 0; i < NPART; ++i) {
+    for (int off = 32; off > 0; off >>= 1) r[i] = wave_max(r[i], __shfl_xor(r[i], off, 64));
+  }
+  if (threadIdx.x != 0) return;
+  if (kind != FIN_RHS && !ctl->active) return;
+  const bool bad = r[8] != 0.0;
+  if (is_euler) {
+    if (ph.lf_scalar) {
+      for (int s = 0; s < 4; ++s) { ctl->alpha[0][s] = r[6]; ctl->alpha[1][s] = r[7]; }
+    } else {
+      ctl->alpha[0][0] = r[0]; ctl->alpha[0][1] = r[1]; ctl->alpha[0][2] = r[1]; ctl->alpha[0][3] = r[2];
+      ctl->alpha[1][0] = r[3]; ctl->alpha[1][1] = r[4]; ctl->alpha[1][2] = r[4]; ctl->alpha[1][3] = r[5];
+    }
+  } else {
+    ctl->alpha[0][0] = r[0];
+    ctl->alpha[1][0] = r[3];
+  }
+  ctl->smax[0] = r[6];
+  ctl->smax[1] = r[7];
+  if (bad) {
+    if (!ctl->bad) ctl->bad_step = ctl->steps;
+    ctl->bad = 1;
+    if (kind != FIN_RHS) ctl->active = 0;
+    return;
+  }
+  if (kind == FIN_STAGE0) {
+    if (ctl->max_steps > 0 && ctl->steps >= ctl->max_steps) { ctl->active = 0; return; }
+    if (ctl->t >= ctl->t_final) { ctl->active = 0; return; }
+    double dt;
+    if (ctl->dt_fixed > 0.0) {
+      dt = ctl->dt_fixed;
+    } else if (ph.dt_rule == 1) {
+      const double h = dim == 2 ? fmin(g.dx, g.dy) : g.dx;
+      dt = ph.cfl * h * h;
+    } else if (dim == 1) {
+      dt = ph.cfl * g.dx / r[6];
+    } else {
+      dt = ph.cfl / (r[6] / g.dx + r[7] / g.dy);
+    }
+    ctl->last = 0;
+    if (ctl->t + dt >= ctl->t_final) { dt = ctl->t_final - ctl->t; ctl->last = 1; }
+    ctl->dt = dt;
+  }
+}
+
+__global__ void k_step_end(DevCtl* ctl) {
+  if (threadIdx.x != 0 || !ctl->active) return;
+  const double dt = ctl->dt;
+  ctl->t = ctl->last ? ctl->t_final : ctl->t + dt;
+  ctl->steps += 1;
+  ctl->dt_min = fmin(ctl->dt_min, dt);
+  ctl->dt_max = fmax(ctl->dt_max, dt);
+  if (ctl->last) ctl->active = 0;
+  if (ctl->max_steps > 0 && ctl->steps >= ctl->max_steps) ctl->active = 0;
+}
+
+// Fixed-order FP64 sums of each component (deterministic for a given size):
+// block b sums the contiguous chunk [b*chunk, (b+1)*chunk) with a fixed tree.
+__global__ __launch_bounds__(256) void k_sum_partial(const double* __restrict__ q, size_t n, size_t chunk,
+                                                     double* __restrict__ part) {
+  const size_t lo = (size_t)blockIdx.x * chunk;
+  const size_t hi = lo + chunk < n ? lo + chunk : n;
+  double s = 0.0;
+  for (size_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += q[i];
+  __shared__ double sm[256];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+}  // namespace za

@@ -1,0 +1,516 @@
+// libza: host side of the C ABI declared in include/za.h.
+//
+// One context = one problem shape on one device and stream.  It owns the
+// RK3 stage states, the x-sweep partial RHS (2D), the wave-speed reduction
+// partials and the device control block (LF speeds, dt, t) that lets whole
+// RK3 steps run without host round trips.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "za.h"
+#include "za_kernels.hpp"
+#include "za_internal.hpp"
+
+using namespace za;
+
+namespace {
+
+const char* kStatusStr[] = {"ok", "invalid argument", "out of device memory", "device error",
+                            "non-finite or non-physical state", "unsupported", "busy"};
+
+int ncomp_of(const za_problem& p) {
+  if (p.system == ZA_EULER) return p.dim == 1 ? 3 : 4;
+  return 1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+za_status za_validate(const za_problem* p, std::string* why) {
+  auto fail = [&](const char* m) { if (why) *why = m; return ZA_ERR_ARG; };
+  if (!p) return fail("problem is NULL");
+  if (p->dim != 1 && p->dim != 2) return fail("dim must be 1 or 2");
+  if (p->system < ZA_ADVECTION || p->system > ZA_BUCKLEY) return fail("unknown system");
+  if (p->nx < 1 || p->ny < 1) return fail("nx and ny must be >= 1");
+  if (p->dim == 1 && p->ny != 1) return fail("ny must be 1 in 1D");
+  if ((long long)p->nx * p->ny > (1LL << 31)) return fail("grid too large");
+  if (!(p->xhi > p->xlo) || (p->dim == 2 && !(p->yhi > p->ylo))) return fail("empty domain");
+  if (p->bc_x < 0 || p->bc_x > 1 || p->bc_y < 0 || p->bc_y > 1) return fail("unknown boundary condition");
+  if (p->system == ZA_EULER && !(p->gamma > 1.0)) return fail("gamma must exceed 1");
+  if (!(p->cfl > 0.0)) return fail("cfl must be positive");
+  if (p->dt_rule < 0 || p->dt_rule > 1) return fail("unknown dt rule");
+  if (p->precision < 0 || p->precision > 1) return fail("unknown precision");
+  if (!(p->p >= 1.0)) return fail("p must be >= 1");
+  if (!(p->eps > 0.0)) return fail("eps must be positive");
+  if (p->affine_invariant && !(p->mu0 > 0.0)) return fail("mu0 must be positive");
+  if (p->precision == ZA_FP32_RECON && (p->eps < 1e-37 || (p->affine_invariant && p->mu0 < 1e-18)))
+    return fail("FP32 reconstruction needs eps >= 1e-37 and mu0 >= 1e-18 (normal FP32 range)");
+  return ZA_OK;
+}
+
+size_t za_state_count(const za_problem* p) {
+  if (za_validate(p, nullptr) != ZA_OK) return 0;
+  return (size_t)ncomp_of(*p) * p->nx * p->ny;
+}
+
+size_t za_workspace_bytes(const za_problem* p) {
+  if (za_validate(p, nullptr) != ZA_OK) return 0;
+  const size_t st = za_state_count(p) * sizeof(double);
+  size_t b = 2 * st;                      // Q1, Q2
+  if (p->dim == 2) b += st;               // L_x
+  b += (size_t)RED_BLOCKS_MAX * NPART * sizeof(double) + 4096 + sizeof(DevCtl);
+  return b;
+}
+
+const char* za_status_str(za_status s) {
+  int i = (int)s;
+  if (i < 0 || i > 6) return "unknown status";
+  return kStatusStr[i];
+}
+
+const char* za_ctx_last_error(const za_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+static za_status hip_fail(za_ctx* c, hipError_t e, const char* what) {
+  c->err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? ZA_ERR_NOMEM : ZA_ERR_DEVICE;
+}
+
+#define ZA_CHECK_LAUNCH(c, what)                              \
+  do {                                                        \
+    hipError_t e_ = hipGetLastError();                        \
+    if (e_ != hipSuccess) return hip_fail((c), e_, (what));   \
+  } while (0)
+
+template <class T>
+static CfgArg<T> make_cfg(const za_problem& p) {
+  CfgArg<T> c;
+  c.w.eps = (T)p.eps;
+  c.w.mu0 = (T)p.mu0;
+  c.w.p = (T)p.p;
+  c.w.ai = p.affine_invariant;
+  c.w.linear = p.linear_weights;
+  return c;
+}
+
+static void timed_begin(za_ctx* c, int cls) {
+  if (!c->timing) return;
+  hipEvent_t e;
+  hipEventCreate(&e);
+  hipEventRecord(e, c->stream);
+  c->ev_open[cls] = e;
+}
+static void timed_end(za_ctx* c, int cls) {
+  if (!c->timing) return;
+  hipEvent_t e;
+  hipEventCreate(&e);
+  hipEventRecord(e, c->stream);
+  c->events[cls].push_back({c->ev_open[cls], e});
+}
+
+template <int SYS, int M, class T, bool GP>
+static void launch_x_t(za_ctx* c, int mode, const SweepArgs& a) {
+  const CfgArg<T> cfg = make_cfg<T>(c->prob);
+  const int nseg = (a.g.nx + XS_CELLS - 1) / XS_CELLS;
+  const long long waves = (long long)a.g.ny * nseg;
+  const unsigned blocks = (unsigned)((waves + 3) / 4);
+  switch (mode) {
+    case MODE_FLUX: hipLaunchKernelGGL((k_sweep_x<SYS, M, T, MODE_FLUX, GP>), dim3(blocks), dim3(256), 0, c->stream, a, cfg); break;
+    case MODE_RHS: hipLaunchKernelGGL((k_sweep_x<SYS, M, T, MODE_RHS, GP>), dim3(blocks), dim3(256), 0, c->stream, a, cfg); break;
+    case MODE_LX: hipLaunchKernelGGL((k_sweep_x<SYS, M, T, MODE_LX, GP>), dim3(blocks), dim3(256), 0, c->stream, a, cfg); break;
+    default: hipLaunchKernelGGL((k_sweep_x<SYS, M, T, MODE_STAGE, GP>), dim3(blocks), dim3(256), 0, c->stream, a, cfg); break;
+  }
+}
+
+template <int SYS, int M, class T, bool GP>
+static void launch_y_t(za_ctx* c, int mode, const SweepArgs& a) {
+  const CfgArg<T> cfg = make_cfg<T>(c->prob);
+  const unsigned bx = (unsigned)((a.g.nx + 63) / 64);
+  const unsigned by = (unsigned)((a.g.ny + 4 * YS_CELLS - 1) / (4 * YS_CELLS));
+  switch (mode) {
+    case MODE_FLUX: hipLaunchKernelGGL((k_sweep_y<SYS, M, T, MODE_FLUX, GP>), dim3(bx, by), dim3(256), 0, c->stream, a, cfg); break;
+    case MODE_RHS: hipLaunchKernelGGL((k_sweep_y<SYS, M, T, MODE_RHS, GP>), dim3(bx, by), dim3(256), 0, c->stream, a, cfg); break;
+    default: hipLaunchKernelGGL((k_sweep_y<SYS, M, T, MODE_STAGE, GP>), dim3(bx, by), dim3(256), 0, c->stream, a, cfg); break;
+  }
+}
+
+// dispatch on (system, dim, precision, generic p)
+template <int SYS, int M>
+static void launch_x_sys(za_ctx* c, int mode, const SweepArgs& a) {
+  const bool gp = c->prob.p != 1.0;
+  if (c->prob.precision == ZA_FP32_RECON) {
+    if (gp) launch_x_t<SYS, M, float, true>(c, mode, a); else launch_x_t<SYS, M, float, false>(c, mode, a);
+  } else {
+    if (gp) launch_x_t<SYS, M, double, true>(c, mode, a); else launch_x_t<SYS, M, double, false>(c, mode, a);
+  }
+}
+template <int SYS, int M>
+static void launch_y_sys(za_ctx* c, int mode, const SweepArgs& a) {
+  const bool gp = c->prob.p != 1.0;
+  if (c->prob.precision == ZA_FP32_RECON) {
+    if (gp) launch_y_t<SYS, M, float, true>(c, mode, a); else launch_y_t<SYS, M, float, false>(c, mode, a);
+  } else {
+    if (gp) launch_y_t<SYS, M, double, true>(c, mode, a); else launch_y_t<SYS, M, double, false>(c, mode, a);
+  }
+}
+
+static void launch_x(za_ctx* c, int mode, const SweepArgs& a) {
+  timed_begin(c, 0);
+  switch (c->prob.system) {
+    case ZA_EULER:
+      if (c->prob.dim == 1) launch_x_sys<SYS_EULER, 3>(c, mode, a); else launch_x_sys<SYS_EULER, 4>(c, mode, a);
+      break;
+    case ZA_ADVECTION: launch_x_sys<SYS_ADV, 1>(c, mode, a); break;
+    case ZA_BURGERS: launch_x_sys<SYS_BURGERS, 1>(c, mode, a); break;
+    default: launch_x_sys<SYS_BUCKLEY, 1>(c, mode, a); break;
+  }
+  timed_end(c, 0);
+}
+
+static void launch_y(za_ctx* c, int mode, const SweepArgs& a) {
+  timed_begin(c, 1);
+  switch (c->prob.system) {
+    case ZA_EULER: launch_y_sys<SYS_EULER, 4>(c, mode, a); break;
+    case ZA_ADVECTION: launch_y_sys<SYS_ADV, 1>(c, mode, a); break;
+    case ZA_BURGERS: launch_y_sys<SYS_BURGERS, 1>(c, mode, a); break;
+    default: launch_y_sys<SYS_BUCKLEY, 1>(c, mode, a); break;
+  }
+  timed_end(c, 1);
+}
+
+static void launch_wave(za_ctx* c, const double* q, int kind, int check_active) {
+  timed_begin(c, 2);
+  const size_t ncell = (size_t)c->prob.nx * c->prob.ny;
+  const int nblk = c->red_blocks;
+  switch (c->prob.system) {
+    case ZA_EULER:
+      if (c->prob.dim == 1)
+        hipLaunchKernelGGL((k_wave_partial<SYS_EULER, 3>), dim3(nblk), dim3(256), 0, c->stream, q, ncell, c->ph, c->ctl, check_active, c->part);
+      else
+        hipLaunchKernelGGL((k_wave_partial<SYS_EULER, 4>), dim3(nblk), dim3(256), 0, c->stream, q, ncell, c->ph, c->ctl, check_active, c->part);
+      break;
+    case ZA_ADVECTION:
+      hipLaunchKernelGGL((k_wave_partial<SYS_ADV, 1>), dim3(nblk), dim3(256), 0, c->stream, q, ncell, c->ph, c->ctl, check_active, c->part);
+      break;
+    case ZA_BURGERS:
+      hipLaunchKernelGGL((k_wave_partial<SYS_BURGERS, 1>), dim3(nblk), dim3(256), 0, c->stream, q, ncell, c->ph, c->ctl, check_active, c->part);
+      break;
+    default:
+      hipLaunchKernelGGL((k_wave_partial<SYS_BUCKLEY, 1>), dim3(nblk), dim3(256), 0, c->stream, q, ncell, c->ph, c->ctl, check_active, c->part);
+      break;
+  }
+  hipLaunchKernelGGL((k_wave_final<4>), dim3(1), dim3(64), 0, c->stream, c->part, nblk, c->ctl, c->geom, c->ph,
+                     c->prob.dim, kind, c->prob.system == ZA_EULER ? 1 : 0);
+  timed_end(c, 2);
+}
+
+__global__ void k_ctl_init(DevCtl* ctl, DevCtl v) {
+  if (threadIdx.x == 0) *ctl = v;
+}
+__global__ void k_ctl_arm(DevCtl* ctl, double dt_fixed, double t_final, long long max_steps) {
+  // start a new stepping sequence from the current (t, steps)
+  if (threadIdx.x != 0) return;
+  ctl->dt_fixed = dt_fixed;
+  ctl->t_final = t_final;
+  ctl->max_steps = max_steps;
+  ctl->active = ctl->bad ? 0 : 1;
+}
+
+static SweepArgs base_args(za_ctx* c) {
+  SweepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.ctl = c->ctl;
+  a.g = c->geom;
+  a.ph = c->ph;
+  return a;
+}
+
+// One RK3 step on the stream (no host synchronisation).
+static za_status enqueue_step(za_ctx* c, double* q) {
+  const double ca[3] = {0.0, 0.75, 1.0 / 3.0};
+  const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
+  const double* in[3] = {q, c->q1, c->q2};
+  double* out[3] = {c->q1, c->q2, q};
+  for (int s = 0; s < 3; ++s) {
+    launch_wave(c, in[s], s == 0 ? FIN_STAGE0 : FIN_STAGEK, 1);
+    SweepArgs a = base_args(c);
+    a.check_active = 1;
+    a.q = in[s];
+    a.qn = q;
+    a.ca = ca[s];
+    a.cb = cb[s];
+    if (c->prob.dim == 1) {
+      a.out = out[s];
+      launch_x(c, MODE_STAGE, a);
+    } else {
+      a.out = c->lx;
+      launch_x(c, MODE_LX, a);
+      a.lx = c->lx;
+      a.out = out[s];
+      launch_y(c, MODE_STAGE, a);
+    }
+  }
+  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, c->stream, c->ctl);
+  ZA_CHECK_LAUNCH(c, "step launch");
+  return ZA_OK;
+}
+
+static DevCtl fresh_ctl() {
+  DevCtl v;
+  std::memset(&v, 0, sizeof(v));
+  v.t = 0.0;
+  v.t_final = std::numeric_limits<double>::infinity();
+  v.dt_min = std::numeric_limits<double>::infinity();
+  v.dt_max = 0.0;
+  v.bad_step = -1;
+  v.active = 0;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+za_status za_ctx_create(const za_problem* p, void* stream, za_ctx** out) {
+  if (!out) return ZA_ERR_ARG;
+  *out = nullptr;
+  std::string why;
+  za_status st = za_validate(p, &why);
+  if (st != ZA_OK) return st;
+  za_ctx* c = new za_ctx();
+  c->prob = *p;
+  c->m = ncomp_of(*p);
+  c->stream = (hipStream_t)stream;
+  hipGetDevice(&c->device);
+  const size_t ncell = (size_t)p->nx * p->ny;
+  const size_t st_bytes = (size_t)c->m * ncell * sizeof(double);
+  c->geom.nx = p->nx;
+  c->geom.ny = p->ny;
+  c->geom.bc_x = p->bc_x;
+  c->geom.bc_y = p->bc_y;
+  c->geom.dx = (p->xhi - p->xlo) / p->nx;
+  c->geom.dy = p->dim == 2 ? (p->yhi - p->ylo) / p->ny : 1.0;
+  c->geom.inv_dx = 1.0 / c->geom.dx;
+  c->geom.inv_dy = 1.0 / c->geom.dy;
+  c->ph.gamma = p->gamma;
+  c->ph.gm1 = p->gamma - 1.0;
+  c->ph.adv[0] = p->adv_speed[0];
+  c->ph.adv[1] = p->adv_speed[1];
+  c->ph.cfl = p->cfl;
+  c->ph.dt_rule = p->dt_rule;
+  c->ph.lf_scalar = p->lf == ZA_LF_SCALAR ? 1 : 0;
+  c->red_blocks = (int)std::min<size_t>(RED_BLOCKS_MAX, std::max<size_t>(1, (ncell + 2047) / 2048));
+  hipError_t e;
+  void* ptr = nullptr;
+  if ((e = hipMalloc(&ptr, st_bytes)) != hipSuccess) { delete c; return ZA_ERR_NOMEM; }
+  c->q1 = (double*)ptr;
+  if ((e = hipMalloc(&ptr, st_bytes)) != hipSuccess) { za_ctx_destroy(c); return ZA_ERR_NOMEM; }
+  c->q2 = (double*)ptr;
+  if (p->dim == 2) {
+    if ((e = hipMalloc(&ptr, st_bytes)) != hipSuccess) { za_ctx_destroy(c); return ZA_ERR_NOMEM; }
+    c->lx = (double*)ptr;
+  }
+  if ((e = hipMalloc(&ptr, (size_t)RED_BLOCKS_MAX * NPART * sizeof(double) + 4096)) != hipSuccess) {
+    za_ctx_destroy(c);
+    return ZA_ERR_NOMEM;
+  }
+  c->part = (double*)ptr;
+  if ((e = hipMalloc(&ptr, sizeof(DevCtl))) != hipSuccess) { za_ctx_destroy(c); return ZA_ERR_NOMEM; }
+  c->ctl = (DevCtl*)ptr;
+  hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, c->stream, c->ctl, fresh_ctl());
+  if ((e = hipGetLastError()) != hipSuccess) { za_ctx_destroy(c); return ZA_ERR_DEVICE; }
+  *out = c;
+  return ZA_OK;
+}
+
+za_status za_ctx_destroy(za_ctx* c) {
+  if (!c) return ZA_ERR_ARG;
+  if (c->stream || true) hipStreamSynchronize(c->stream);
+  for (int k = 0; k < 3; ++k) {
+    for (auto& pr : c->events[k]) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
+  }
+  if (c->q1) hipFree(c->q1);
+  if (c->q2) hipFree(c->q2);
+  if (c->lx) hipFree(c->lx);
+  if (c->part) hipFree(c->part);
+  if (c->ctl) hipFree(c->ctl);
+  delete c;
+  return ZA_OK;
+}
+
+za_status za_ctx_set_stream(za_ctx* c, void* stream) {
+  if (!c) return ZA_ERR_ARG;
+  c->stream = (hipStream_t)stream;
+  return ZA_OK;
+}
+
+za_status za_rhs(za_ctx* c, const double* q, double* rhs) {
+  if (!c || !q || !rhs || q == rhs) return ZA_ERR_ARG;
+  launch_wave(c, q, FIN_RHS, 0);
+  SweepArgs a = base_args(c);
+  a.q = q;
+  a.out = rhs;
+  launch_x(c, MODE_RHS, a);
+  if (c->prob.dim == 2) {
+    a.lx = rhs;
+    launch_y(c, MODE_RHS, a);
+  }
+  ZA_CHECK_LAUNCH(c, "rhs launch");
+  return ZA_OK;
+}
+
+za_status za_rhs_fluxes(za_ctx* c, const double* q, double* fx, double* fy) {
+  if (!c || !q || !fx) return ZA_ERR_ARG;
+  launch_wave(c, q, FIN_RHS, 0);
+  SweepArgs a = base_args(c);
+  a.q = q;
+  a.out = fx;
+  launch_x(c, MODE_FLUX, a);
+  if (c->prob.dim == 2 && fy) {
+    a.out = fy;
+    launch_y(c, MODE_FLUX, a);
+  }
+  ZA_CHECK_LAUNCH(c, "flux launch");
+  return ZA_OK;
+}
+
+static za_status read_ctl(za_ctx* c, DevCtl* h) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "synchronise");
+  e = hipMemcpy(h, c->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "read control block");
+  return ZA_OK;
+}
+
+za_status za_step(za_ctx* c, double* q, double dt, double* dt_used) {
+  if (!c || !q) return ZA_ERR_ARG;
+  if (!(dt > 0.0) && !(dt <= 0.0)) return ZA_ERR_ARG;  // NaN
+  hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, c->stream, c->ctl, fresh_ctl());
+  hipLaunchKernelGGL(k_ctl_arm, dim3(1), dim3(64), 0, c->stream, c->ctl, dt > 0.0 ? dt : 0.0,
+                     std::numeric_limits<double>::infinity(), 1LL);
+  za_status st = enqueue_step(c, q);
+  if (st != ZA_OK) return st;
+  if (dt_used) {
+    DevCtl h;
+    if ((st = read_ctl(c, &h)) != ZA_OK) return st;
+    *dt_used = h.dt;
+    if (h.bad) return ZA_ERR_NONFINITE;
+  }
+  return ZA_OK;
+}
+
+za_status za_solve(za_ctx* c, double* q, double t_final, int64_t max_steps, za_solve_info* info) {
+  if (!c || !q) return ZA_ERR_ARG;
+  if (!(t_final > 0.0) && max_steps <= 0) return ZA_ERR_ARG;
+  if (t_final != t_final) return ZA_ERR_ARG;
+  const auto& p = c->prob;
+  DevCtl h;
+  za_status st;
+  hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, c->stream, c->ctl, fresh_ctl());
+  const int chunk = c->chunk_steps > 0 ? c->chunk_steps : 32;
+  if (t_final > 0.0 && p.dt_rule == ZA_DT_CFL_H2) {
+    // fixed dt = cfl h^2: n equal steps, the last one lands on t_final
+    const double h2 = p.dim == 2 ? std::min(c->geom.dx, c->geom.dy) : c->geom.dx;
+    const double dt = p.cfl * h2 * h2;
+    const int64_t n = (int64_t)std::ceil(t_final / dt * (1.0 - 1e-12));
+    int64_t n_run = n;
+    if (max_steps > 0 && max_steps < n) n_run = max_steps;
+    const int64_t n_equal = std::min<int64_t>(n_run, n - 1);
+    hipLaunchKernelGGL(k_ctl_arm, dim3(1), dim3(64), 0, c->stream, c->ctl, dt,
+                       std::numeric_limits<double>::infinity(), (long long)n_equal);
+    for (int64_t s = 0; s < n_equal; ++s) {
+      if ((st = enqueue_step(c, q)) != ZA_OK) return st;
+      if ((s + 1) % (64 * chunk) == 0) {
+        if ((st = read_ctl(c, &h)) != ZA_OK) return st;
+        if (h.bad) break;
+      }
+    }
+    if (n_run == n) {
+      const double last = t_final - (double)(n - 1) * dt;
+      hipLaunchKernelGGL(k_ctl_arm, dim3(1), dim3(64), 0, c->stream, c->ctl, last,
+                         std::numeric_limits<double>::infinity(), (long long)n);
+      if ((st = enqueue_step(c, q)) != ZA_OK) return st;
+    }
+    if ((st = read_ctl(c, &h)) != ZA_OK) return st;
+    if (n_run == n && !h.bad) h.t = t_final;
+  } else {
+    const double tf = t_final > 0.0 ? t_final : std::numeric_limits<double>::infinity();
+    hipLaunchKernelGGL(k_ctl_arm, dim3(1), dim3(64), 0, c->stream, c->ctl, 0.0, tf,
+                       (long long)(max_steps > 0 ? max_steps : 0));
+    while (true) {
+      for (int s = 0; s < chunk; ++s)
+        if ((st = enqueue_step(c, q)) != ZA_OK) return st;
+      if ((st = read_ctl(c, &h)) != ZA_OK) return st;
+      if (!h.active || h.bad) break;
+    }
+  }
+  if (info) {
+    info->steps = h.steps;
+    info->t = h.t;
+    info->dt_min = h.dt_min;
+    info->dt_max = h.dt_max;
+    info->nonfinite_step = h.bad ? h.bad_step : -1;
+  }
+  return h.bad ? ZA_ERR_NONFINITE : ZA_OK;
+}
+
+za_status za_conserved_sums(za_ctx* c, const double* q, double* sums) {
+  if (!c || !q || !sums) return ZA_ERR_ARG;
+  const size_t ncell = (size_t)c->prob.nx * c->prob.ny;
+  const int nblk = (int)std::min<size_t>(RED_BLOCKS_MAX * NPART, std::max<size_t>(1, (ncell + 4095) / 4096));
+  const size_t chunk = (ncell + nblk - 1) / nblk;
+  std::vector<double> part(nblk);
+  for (int comp = 0; comp < c->m; ++comp) {
+    hipLaunchKernelGGL(k_sum_partial, dim3(nblk), dim3(256), 0, c->stream, q + comp * ncell, ncell, chunk, c->part);
+    ZA_CHECK_LAUNCH(c, "sum launch");
+    hipError_t e = hipMemcpyAsync(part.data(), c->part, nblk * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "copy sums");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "synchronise");
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[b];
+    sums[comp] = s;
+  }
+  return ZA_OK;
+}
+
+za_status za_ctx_set_timing(za_ctx* c, int32_t enable) {
+  if (!c) return ZA_ERR_ARG;
+  c->timing = enable != 0;
+  return ZA_OK;
+}
+
+za_status za_ctx_kernel_times(za_ctx* c, double* avg_ms, int64_t* counts) {
+  if (!c || !avg_ms) return ZA_ERR_ARG;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "synchronise");
+  for (int k = 0; k < 3; ++k) {
+    double tot = 0.0;
+    for (auto& pr : c->events[k]) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, pr.first, pr.second);
+      tot += ms;
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+    const size_t n = c->events[k].size();
+    avg_ms[k] = n ? tot / (double)n : 0.0;
+    if (counts) counts[k] = (int64_t)n;
+    c->events[k].clear();
+  }
+  return ZA_OK;
+}
+
+}  // extern "C"
