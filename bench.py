@@ -1,0 +1,191 @@
+"""Benchmark: WENO-ZA6 interface reconstructions per second on one MI355X.
+
+Workload (N = 1): 2D Euler, gamma = 1.4, 2048 x 2048 cells on [0,1]^2,
+transmissive boundaries, seeded four-quadrant Riemann data (seed 0),
+characteristic-wise WENO-ZA6 dimension by dimension, SSP-RK3 at CFL 0.5,
+FP64.  One "step" is one full SSP-RK3 step (three right-hand sides, each an
+x-sweep and a y-sweep over every interface plus the wave-speed reductions);
+the default times the configuration's 200 steps from t = 0.
+
+value = interface reconstructions per second = 3 * ((nx+1) ny + nx (ny+1))
+        * steps / wall time, with the state resident in HBM.
+Also reported: the same run with FP32 reconstruction and its density error
+against the FP64 run, the dominant kernel against the FP64 vector peak, and
+the oracle timed on the host cores over a bounded sample of the workload.
+
+Usage:  python bench.py [--gpus 1] [--steps 200] [--warmup 10]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic FLOPs of one sweep launch, from the oracle's counting scalar
+# (python -m oracle.count_flops; checked by tests/test_flop_counts.py):
+# per interface, per cell for the physical flux, per cell for the flux
+# difference / accumulation / RK3 stage.
+FLOPS_2D = {
+    "x": {"interface": 1371.0, "cell_flux": 15.0, "cell_update": 8},
+    "y": {"interface": 1371.0, "cell_flux": 15.0, "cell_update": 32},
+}
+PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (packed issue)
+PEAK_HBM_GBS = 8000.0
+
+
+def ir_per_rhs(nx, ny):
+    return (nx + 1) * ny + nx * (ny + 1)
+
+
+def sweep_flops(nx, ny, d):
+    f = FLOPS_2D[d]
+    nir = (nx + 1) * ny if d == "x" else nx * (ny + 1)
+    cells = nx * ny
+    return nir * f["interface"] + cells * (f["cell_flux"] + f["cell_update"])
+
+
+def sweep_bytes(nx, ny, d):
+    """Algorithmic HBM bytes of one sweep launch: x reads Q and writes L_x;
+    y reads Q, L_x and Q^n and writes the new stage state (FP64, m = 4)."""
+    cells = nx * ny
+    return cells * 32 * (2 if d == "x" else 4)
+
+
+def run_gpu(P, q0_np, steps, warmup, torch, Context):
+    dev = torch.device("cuda:0")
+    q0 = torch.from_numpy(q0_np).to(dev)
+    q = q0.clone()
+    ctx = Context(P)
+    if warmup > 0:
+        ctx.solve(q, 0.0, warmup)
+    q.copy_(q0)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = ctx.solve(q, 0.0, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    avg_ms, counts = ctx.kernel_times()
+    ctx.set_timing(False)
+    ctx.close()
+    return q, t1 - t0, info, avg_ms, counts
+
+
+def cpu_baseline(P, q0_np, seconds):
+    """The oracle (as it stands) on the host cores: repeated full 2048^2
+    right-hand sides until `seconds` have elapsed (at least one)."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    oracle.set_threads(threads)
+    used = oracle.get_threads()
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.rhs(P, q0_np)
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    irs = n * ir_per_rhs(P.nx, P.ny) / dt
+    return {"value": irs, "unit": "IR/s", "cores": used, "kind": "oracle",
+            "sample": f"{n} full right-hand side(s) of the 2D Euler {P.nx}x{P.ny} workload "
+                      f"(one RK3 stage each, {ir_per_rhs(P.nx, P.ny)} IR) in {dt:.1f} s, FP64, "
+                      f"OpenMP over rows"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one MI355X "
+              f"(the multi-GPU slab decomposition is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2603_26272_amd import workloads as W
+    from paper_2603_26272_amd.za import Context
+
+    torch.cuda.set_device(0)
+    P, q0 = W.quadrants_2d(args.seed, args.n)
+    nx, ny = P.nx, P.ny
+    ir_step = 3 * ir_per_rhs(nx, ny)
+
+    q64, wall, info, avg_ms, counts = run_gpu(P, q0, args.steps, args.warmup, torch, Context)
+    assert info["steps"] == args.steps, info
+    value = ir_step * args.steps / wall
+    ms_step = wall / args.steps * 1e3
+
+    names = ["x-sweep", "y-sweep", "wave-speed"]
+    dom = 0 if avg_ms[0] >= avg_ms[1] else 1
+    d = "x" if dom == 0 else "y"
+    fl = sweep_flops(nx, ny, d)
+    achieved = fl / (avg_ms[dom] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "kernel": f"k_sweep_{d} (2D Euler FP64)",
+                "avg_launch_ms": avg_ms[dom], "launches": counts[dom],
+                "algorithmic_flop_per_launch": fl,
+                "algorithmic_bytes_per_launch": sweep_bytes(nx, ny, d)}
+    kernels = {names[k]: {"avg_ms": avg_ms[k], "launches": counts[k]} for k in range(3)}
+    for k, dd in ((0, "x"), (1, "y")):
+        kernels[names[k]]["tflops"] = sweep_flops(nx, ny, dd) / (avg_ms[k] * 1e-3) / 1e12 if avg_ms[k] else None
+
+    out = {
+        "metric": "WENO-ZA6 interface recons/s (2D Euler, FP64 vs FP32) + served p50/p99 latency",
+        "value": value,
+        "unit": "IR/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded four-quadrant Riemann data)",
+        "config": {"workload": f"2D Euler {nx}x{ny} four-quadrant Riemann, transmissive, "
+                               f"WENO-ZA6 characteristic-wise, SSP-RK3 CFL 0.5, FP64",
+                   "nx": nx, "ny": ny, "seed": args.seed, "ir_per_step": ir_step,
+                   "t_final": info["t"]},
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+
+    if not args.no_fp32:
+        P32 = P.fp32()
+        q32, wall32, info32, avg32, cnt32 = run_gpu(P32, q0, args.steps, args.warmup, torch, Context)
+        r64 = q64[0].double()
+        r32 = q32[0].double()
+        e = (r32 - r64).abs()
+        out["fp32"] = {"value": ir_step * args.steps / wall32, "unit": "IR/s",
+                       "ms_per_step": wall32 / args.steps * 1e3,
+                       "density_err_vs_fp64": {"l1": float(e.mean()), "linf": float(e.max())},
+                       "avg_launch_ms": {names[k]: avg32[k] for k in range(3)},
+                       "speedup_vs_fp64": wall / wall32}
+
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(P, q0, args.cpu_seconds)
+        cb["gpu_over_cpu"] = value / cb["value"]
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -80,7 +80,7 @@ def lib():
         L.orc_solve.restype = C.c_int
         L.orc_solve.argtypes = [PP, _DP, C.c_double, C.c_int64, C.POINTER(C.c_int64), _DP]
         L.orc_count_ops.restype = C.c_int64
-        L.orc_count_ops.argtypes = [PP, _DP, C.POINTER(C.c_int64)]
+        L.orc_count_ops.argtypes = [PP, _DP, C.c_int, C.POINTER(C.c_int64)]
         L.orc_euler_eigen.restype = None
         L.orc_euler_eigen.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                       C.c_double, C.c_double, _DP, _DP]
@@ -241,13 +241,13 @@ def solve(pb, q, t_final, max_steps=0):
     return q, steps.value, t.value, st
 
 
-def count_ops(pb, q):
-    """Algorithmic op counts of one RHS (interface work + per-cell fluxes).
-    Returns (n_interfaces, dict)."""
+def count_ops(pb, q, dir_mask=3):
+    """Algorithmic op counts of the interface fluxes of one RHS (interface
+    work + physical flux per cell incl. ghosts).  Returns (n_interfaces, dict)."""
     P = _problem(pb)
     q = _state(pb, q)
     cnt = (C.c_int64 * 5)()
-    nir = lib().orc_count_ops(C.byref(P), _ptr(q), cnt)
+    nir = lib().orc_count_ops(C.byref(P), _ptr(q), int(dir_mask), cnt)
     return nir, {"add": cnt[0], "mul": cnt[1], "div": cnt[2], "sqrt": cnt[3], "other": cnt[4]}
 
 

@@ -874,14 +874,16 @@ int orc_solve(const orc_problem* p, double* q, double t_final, int64_t max_steps
   return bad ? 4 : 0;
 }
 
-/* Algorithmic operation counts of one RHS evaluation (both sweeps in 2D),
- * via the counting scalar.  counts[0..4] = add/sub, mul, div, sqrt, other
- * (abs/max/compare/pow).  Returns the number of interface reconstructions
- * (interfaces over all sweeps), or -1 on error.  Per-cell work (physical
- * flux) and the interface work are included; the wave-speed reduction, the
- * flux difference and the RK3 combination are FP64 and counted separately
- * by the caller from their closed forms. */
-int64_t orc_count_ops(const orc_problem* p, const double* q, int64_t* counts) {
+/* Algorithmic operation counts of the interface fluxes of one RHS
+ * evaluation, via the counting scalar.  dir_mask bit 0: x-sweep, bit 1:
+ * y-sweep (2D).  counts[0..4] = add/sub, mul, div, sqrt, other (abs, max,
+ * compare, pow).  The physical flux is evaluated once per cell of each line
+ * including its six ghost cells; the caller separates per-cell and
+ * per-interface work by counting two sizes.  Returns the number of interface
+ * reconstructions counted, or -1 on error.  The wave-speed reduction, the
+ * flux difference and the RK3 combination are FP64 closed forms, counted by
+ * the caller. */
+int64_t orc_count_ops(const orc_problem* p, const double* q, int dir_mask, int64_t* counts) {
   Ctx C; if (make_ctx(p, &C)) return -1;
 #ifdef _OPENMP
   int saved = omp_get_max_threads();
@@ -890,12 +892,15 @@ int64_t orc_count_ops(const orc_problem* p, const double* q, int64_t* counts) {
   const orc_problem& P = C.P;
   double ax[4], ay[4], s;
   wave_speeds(P, q, 0, ax, &s);
+  wave_speeds(P, q, 1, ay, &s);
   std::memset(&g_ops, 0, sizeof(g_ops));
-  std::vector<double> fx((size_t)C.m * P.ny * (P.nx + 1));
-  sweep_fluxes<Cnt>(C, q, 0, ax, fx.data());
-  int64_t nir = (int64_t)(P.nx + 1) * P.ny;
-  if (P.dim == 2) {
-    wave_speeds(P, q, 1, ay, &s);
+  int64_t nir = 0;
+  if (dir_mask & 1) {
+    std::vector<double> fx((size_t)C.m * P.ny * (P.nx + 1));
+    sweep_fluxes<Cnt>(C, q, 0, ax, fx.data());
+    nir += (int64_t)(P.nx + 1) * P.ny;
+  }
+  if (P.dim == 2 && (dir_mask & 2)) {
     std::vector<double> fy((size_t)C.m * (P.ny + 1) * P.nx);
     sweep_fluxes<Cnt>(C, q, 1, ay, fy.data());
     nir += (int64_t)P.nx * (P.ny + 1);

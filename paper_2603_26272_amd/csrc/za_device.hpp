@@ -15,119 +15,228 @@
 namespace za {
 
 // ---------------------------------------------------------------------------
-// Parameters of the nonlinear weights (eq:weight_nonlinear, eq:aimu).
+// Parameters of the nonlinear weights (eq:weight_nonlinear, eq:aimu), already
+// rescaled for the exact power-of-two scaling used below.
 // ---------------------------------------------------------------------------
 template <class T>
 struct WeightCfg {
-  T eps;      // sensitivity epsilon
-  T mu0;      // mu_0 of the affine-invariant descaler
+  T eps16;    // 16 epsilon   (Z weights, indicators of 2v scaled by 4)
+  T eps4;     // 4 epsilon    (Ai weights after dividing by mu(2v)^2)
+  T mu0x2;    // 2 mu_0       (descaler of 2v)
   T p;        // power parameter (1 on the fast path)
   int ai;     // 1: affine-invariant descaler
   int linear; // 1: omega = d
 };
 
-template <class T> __device__ __forceinline__ T rcp_fast(T x);
-template <> __device__ __forceinline__ float rcp_fast<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ __forceinline__ double rcp_fast<double>(double x) { return 1.0 / x; }
+// Weight variants compiled as separate kernels: the paper's Z weights with
+// p = 1 and mu = 1 (the fast path), or everything else (Ai descaler, p != 1,
+// linear weights) decided at run time.
+enum { WV_Z1 = 0, WV_GENERAL = 1 };
+
+// Reciprocal and quotient from the hardware reciprocal estimate refined by
+// two Newton-Raphson steps (r <- r + r (1 - x r)), then one residual
+// correction of the quotient (q <- q + r (a - x q)).  Operands stay far from
+// the denormal and overflow ranges here (positive normal densities and
+// weight sums >= 1e-156), so no exponent scaling is needed.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double div_nr(double a, double x) {
+  const double r = rcp_nr(x);
+  const double q = a * r;
+  return fma(fma(-x, q, a), r, q);
+}
+__device__ __forceinline__ float rcp_nr(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float div_nr(float a, float x) { return a * __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------------------
-// One WENO-ZA6 reconstruction of h at x_{i+1/2} from v0..v5 = f_{i-2..i+3}
-// (Section 3: r = 3).  The negative split flux calls this with the six
+// One WENO-ZA6 reconstruction at x_{i+1/2} (Section 3: r = 3).
+//
+// Input: s = (s0..s5) = 2 (f_{i-2}, .., f_{i+3}), i.e. twice the split flux
+// values, which the caller forms with one FMA each (g +- alpha w).  Output:
+// twice the reconstructed flux.  The negative split flux passes its six
 // values in reverse order (mirror symmetry about x_{i+1/2}, Section 2).
 //
 //  candidates  q_k = <c_k, f_k>, c_k = (2,-7,11)/6, (-1,5,2)/6, (2,5,-1)/6,
 //              (11,-7,2)/6                         (eq:subflux_S6_coeffs)
-//  indicators  beta_k = (13/12) D2_k^2 + (1/4) D1_k^2, the Jiang-Shu form of
-//              eq:SI for quadratics (D2 the second difference, D1 twice the
-//              slope of p_k at x_i); k = 3 is the downwind beta_d measured on
-//              I_i.  This sum of squares equals the printed quadratic forms
-//              <f_k, B_k f_k> (eq:SI_S6) exactly and is never negative.
+//  indicators  beta_k = (13/12) D2_k^2 + (1/4) D1_k^2: eq:SI for quadratics
+//              (D2 the second difference, D1 twice the slope of p_k at x_i);
+//              k = 3 is the downwind beta_d, measured on I_i.  This sum of
+//              squares equals the printed quadratic forms <f_k, B_k f_k>
+//              (eq:SI_S6) and is never negative.
 //  downwind    beta_3 = (beta_0 + beta_1 + beta_2 + beta_d)/4 (eq:SI_downwind)
-//  global      tau = <c_tau, f>^2, c_tau = (-1,5,-10,10,-5,1)   (eq:GSI)
+//  global      tau = <c_tau, f>^2 with <c_tau, f> the fifth difference
+//              (c_tau = (-1,5,-10,10,-5,1), eq:GSI)
 //  weights     alpha_k = d_k (1 + tau/(beta_k + eps mu^2)), d = (1,9,9,1)/20,
-//              omega_k = alpha_k / sum alpha  (eq:weights_unnormalized with
-//              L = q = 1, p = 1, eq:weights_general)
+//              omega_k = alpha_k / sum alpha (eq:weights_unnormalized with
+//              L = q = 1, p = 1; eq:weights_general)
 //
-// FP64, p = 1: the weights are evaluated over a common denominator,
-//   f = sum_k d_k (b_k + tau) P_k q_k / sum_k d_k (b_k + tau) P_k,
-//   b_k = beta_k + eps, P_k = prod_{j != k} b_j,
-// which is algebraically identical and needs one division instead of five.
-// b_k >= eps = 1e-40 keeps every product above 1e-161 (no underflow in FP64);
-// with the Ai descaler the indicators are first divided by mu^2, which
-// leaves Gamma_k unchanged and restores b_k >= eps.  FP32 keeps the direct
-// form (products of three indicators would underflow at eps = 1e-20) with
-// hardware reciprocals.
+// Exact rescaling.  With s = 2f the code forms B_k = (13/3) D2(s)^2 + D1(s)^2
+// = 16 beta_k(f) and T = (2 D5(s))^2 = 16 tau(f); multiplying by powers of
+// two is exact in binary floating point, so tau/(beta + eps) is evaluated as
+// T/(B + 16 eps) with identical rounding.  (Ai: mu(s) = 2 mu(f) with 2 mu_0,
+// then T/mu(s)^2 and B/mu(s)^2 are 4 tau/mu^2 and 4 beta/mu^2, so 4 eps.)
+//
+// FP64 fast path: the weights are evaluated over a common denominator,
+//   2f = sum_k d_k (b_k + T) P_k q_k / sum_k d_k (b_k + T) P_k,
+//   b_k = B_k + 16 eps, P_k = prod_{j != k} b_j  (the 1/20 cancels),
+// algebraically identical to the normalised weights with one division
+// instead of five.  b_k >= 1.6e-39 keeps every product above 1e-156, so
+// nothing underflows; the products overflow only for flux values beyond
+// about 1e37, and the resulting non-finite state is reported.  FP32 keeps the
+// direct form (three indicators at 16 eps_32 would underflow) with the
+// hardware reciprocal.
 // ---------------------------------------------------------------------------
-template <class T, bool GENERIC_P>
-__device__ __forceinline__ T za6(T v0, T v1, T v2, T v3, T v4, T v5, const WeightCfg<T>& w) {
-  const T sixth = T(1) / T(6);
-  T q0 = (T(2) * v0 - T(7) * v1 + T(11) * v2) * sixth;
-  T q1 = (-v1 + T(5) * v2 + T(2) * v3) * sixth;
-  T q2 = (T(2) * v2 + T(5) * v3 - v4) * sixth;
-  T q3 = (T(11) * v3 - T(7) * v4 + T(2) * v5) * sixth;
-  if (w.linear) {
-    return (q0 + T(9) * q1 + T(9) * q2 + q3) * (T(1) / T(20));
+template <class T, int WV>
+__device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const WeightCfg<T>& w) {
+  const T c13 = T(1) / T(3), c16 = T(1) / T(6), c56 = T(5) / T(6), c76 = T(7) / T(6),
+          c116 = T(11) / T(6);
+  const T q0 = fma(c116, s2, fma(-c76, s1, c13 * s0));
+  const T q1 = fma(c13, s3, fma(c56, s2, -c16 * s1));
+  const T q2 = fma(-c16, s4, fma(c56, s3, c13 * s2));
+  const T q3 = fma(c13, s5, fma(-c76, s4, c116 * s3));
+  if (WV == WV_GENERAL && w.linear) {
+    return (q0 + q3 + T(9) * (q1 + q2)) * T(0.05);
   }
-  const T c13 = T(13) / T(12), c14 = T(0.25);
-  T a = v0 - T(2) * v1 + v2, b = v0 - T(4) * v1 + T(3) * v2;
-  T be0 = c13 * a * a + c14 * b * b;
-  a = v1 - T(2) * v2 + v3; b = v1 - v3;
-  T be1 = c13 * a * a + c14 * b * b;
-  a = v2 - T(2) * v3 + v4; b = T(3) * v2 - T(4) * v3 + v4;
-  T be2 = c13 * a * a + c14 * b * b;
-  a = v3 - T(2) * v4 + v5; b = T(-5) * v3 + T(8) * v4 - T(3) * v5;
-  T bed = c13 * a * a + c14 * b * b;
-  T be3 = T(0.25) * (be0 + be1 + be2 + bed);
-  T t5 = (v5 - v0) + T(5) * (v1 - v4) + T(10) * (v3 - v2);
-  T tau = t5 * t5;
-  T eps = w.eps;
-  if (w.ai) {
-    T mean = (v0 + v1 + v2 + v3 + v4 + v5) * sixth;
-    T mu = (fabs(v0 - mean) + fabs(v1 - mean) + fabs(v2 - mean) + fabs(v3 - mean) +
-            fabs(v4 - mean) + fabs(v5 - mean)) * sixth + w.mu0;
-    T imu2 = T(1) / (mu * mu);
-    be0 *= imu2; be1 *= imu2; be2 *= imu2; be3 *= imu2; tau *= imu2;
+  const T d0 = s1 - s0, d1 = s2 - s1, d2 = s3 - s2, d3 = s4 - s3, d4 = s5 - s4;
+  const T e0 = d1 - d0, e1 = d2 - d1, e2 = d3 - d2, e3 = d4 - d3;
+  const T g0 = fma(T(3), d1, -d0);       // s0 - 4 s1 + 3 s2
+  const T g1 = d1 + d2;                  // -(s1 - s3)
+  const T g2 = fma(T(3), d2, -d3);       // -(3 s2 - 4 s3 + s4)
+  const T g3 = fma(T(5), d3, T(-3) * d4);// -5 s3 + 8 s4 - 3 s5
+  const T k133 = T(13) / T(3);
+  T B0 = fma(k133 * e0, e0, g0 * g0);
+  T B1 = fma(k133 * e1, e1, g1 * g1);
+  T B2 = fma(k133 * e2, e2, g2 * g2);
+  const T Bd = fma(k133 * e3, e3, g3 * g3);
+  T B3 = T(0.25) * ((B0 + B1) + (B2 + Bd));
+  const T t5 = (e3 - e0) + T(3) * (e1 - e2);   // fifth difference
+  const T t2 = t5 + t5;
+  T tau = t2 * t2;
+  T eps = w.eps16;
+  if (WV == WV_GENERAL && w.ai) {
+    const T mean = (s0 + s1 + s2 + s3 + s4 + s5) * c16;
+    const T mu = (fabs(s0 - mean) + fabs(s1 - mean) + fabs(s2 - mean) + fabs(s3 - mean) +
+                  fabs(s4 - mean) + fabs(s5 - mean)) * c16 + w.mu0x2;
+    const T imu2 = rcp_nr(mu * mu);
+    B0 *= imu2; B1 *= imu2; B2 *= imu2; B3 *= imu2; tau *= imu2;
+    eps = w.eps4;
   }
-  T b0 = be0 + eps, b1 = be1 + eps, b2 = be2 + eps, b3 = be3 + eps;
-  if (GENERIC_P || sizeof(T) == 4) {
-    T g0 = tau * rcp_fast<T>(b0), g1 = tau * rcp_fast<T>(b1);
-    T g2 = tau * rcp_fast<T>(b2), g3 = tau * rcp_fast<T>(b3);
-    if (GENERIC_P) {
-      g0 = pow(g0, w.p); g1 = pow(g1, w.p); g2 = pow(g2, w.p); g3 = pow(g3, w.p);
+  const T b0 = B0 + eps, b1 = B1 + eps, b2 = B2 + eps, b3 = B3 + eps;
+  if (WV == WV_GENERAL || sizeof(T) == 4) {
+    T g0w = tau * rcp_nr(b0), g1w = tau * rcp_nr(b1), g2w = tau * rcp_nr(b2), g3w = tau * rcp_nr(b3);
+    if (WV == WV_GENERAL && w.p != T(1)) {
+      g0w = pow(g0w, w.p); g1w = pow(g1w, w.p); g2w = pow(g2w, w.p); g3w = pow(g3w, w.p);
     }
-    T a0 = T(1) + g0, a1 = T(9) * (T(1) + g1), a2 = T(9) * (T(1) + g2), a3 = T(1) + g3;
-    return (a0 * q0 + a1 * q1 + a2 * q2 + a3 * q3) * rcp_fast<T>(a0 + a1 + a2 + a3);
+    const T a0 = T(1) + g0w, a1 = T(9) * (T(1) + g1w), a2 = T(9) * (T(1) + g2w), a3 = T(1) + g3w;
+    return div_nr(fma(a0, q0, fma(a1, q1, fma(a2, q2, a3 * q3))), (a0 + a1) + (a2 + a3));
   } else {
-    T p01 = b0 * b1, p23 = b2 * b3;
-    T e0 = (b0 + tau) * (b1 * p23);
-    T e1 = T(9) * (b1 + tau) * (b0 * p23);
-    T e2 = T(9) * (b2 + tau) * (p01 * b3);
-    T e3 = (b3 + tau) * (p01 * b2);
-    return (e0 * q0 + e1 * q1 + e2 * q2 + e3 * q3) / (e0 + e1 + e2 + e3);
+    const T p01 = b0 * b1, p23 = b2 * b3;
+    const T n01 = T(9) * p01, n23 = T(9) * p23;
+    const T w0 = (b0 + tau) * (b1 * p23);
+    const T w1 = (b1 + tau) * (b0 * n23);
+    const T w2 = (b2 + tau) * (n01 * b3);
+    const T w3 = (b3 + tau) * (p01 * b2);
+    return div_nr(fma(w0, q0, fma(w1, q1, fma(w2, q2, w3 * q3))), (w0 + w1) + (w2 + w3));
   }
 }
 
-// Both Lax-Friedrichs halves of one field at one interface (eq:LF):
-// g^{+-}_j = (g_j +- a w_j)/2; F = R^+(g^+_{i-2..i+3}) + R^+(g^-_{i+3..i-2}).
-template <class T, bool GP>
+// Both Lax-Friedrichs halves of one characteristic field at one interface
+// (eq:LF): with s^{+-}_j = g_j +- a w_j = 2 f^{+-}_j,
+// F = (R(s^+_{i-2..i+3}) + R(s^-_{i+3..i-2})) / 2 where R returns twice the
+// reconstruction.
+template <class T, int WV>
 __device__ __forceinline__ T split_pair(const T (&w)[6], const T (&g)[6], T a, const WeightCfg<T>& cfg) {
   T p[6], m[6];
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    p[j] = T(0.5) * (g[j] + a * w[j]);
-    m[j] = T(0.5) * (g[j] - a * w[j]);
+    p[j] = fma(a, w[j], g[j]);
+    m[j] = fma(-a, w[j], g[j]);
   }
-  return za6<T, GP>(p[0], p[1], p[2], p[3], p[4], p[5], cfg) +
-         za6<T, GP>(m[5], m[4], m[3], m[2], m[1], m[0], cfg);
+  return T(0.5) * (za6<T, WV>(p[0], p[1], p[2], p[3], p[4], p[5], cfg) +
+                   za6<T, WV>(m[5], m[4], m[3], m[2], m[1], m[0], cfg));
 }
 
 // ---------------------------------------------------------------------------
-// Characteristic-wise WENO-ZA6 flux of the Euler equations at one interface,
-// in the sweep-normal frame: component 1 of the state is the normal momentum
-// and (for M = 4) component 2 the tangential one.  The y-sweep permutes its
-// state into this frame and the result back; the two tangential-velocity
-// fields share one eigenvalue and one LF speed, so the reconstruction does
-// not depend on their order.
+// Per-cell records.  Everything the interface fluxes need from one cell is
+// computed once per cell and sweep (point values f_j = f(Q_j), Section 2):
+// the state, the physical flux and the Roe ingredients, in the sweep-normal
+// frame (component 1 = normal momentum, component 2 = tangential momentum).
+// Records live in LDS as structure of arrays, field f of a cell at
+// rec[f * fs + offset].
+//   Euler M = 4: rho, m_n, m_t, E, F1, F2, F3, sqrt(rho)   (8)
+//   Euler M = 3: rho, m_n, E, F1, F2, sqrt(rho)            (6)
+//   scalar:      u, f(u)                                  (2)
+// (F0 = m_n is not stored; the Roe ingredients 1/rho and H of the two cells
+// next to an interface are recomputed there, which keeps the LDS ring of the
+// y-sweep small enough for three blocks per compute unit.)
+// ---------------------------------------------------------------------------
+template <int M> struct RecLayout;
+template <> struct RecLayout<4> {
+  enum { NF = 8, Q0 = 0, Q1 = 1, Q2 = 2, E = 3, F1 = 4, F2 = 5, F3 = 6, SR = 7 };
+};
+template <> struct RecLayout<3> {
+  enum { NF = 6, Q0 = 0, Q1 = 1, Q2 = -1, E = 2, F1 = 3, F2 = -1, F3 = 4, SR = 5 };
+};
+
+// Build the record of one Euler cell from its (frame-permuted) state.
+template <class T, int M>
+__device__ __forceinline__ void euler_record(const double (&qd)[M], T gm1, T* rec, int fs) {
+  typedef RecLayout<M> Lo;
+  const T q0 = (T)qd[0], q1 = (T)qd[1], E = (T)qd[M - 1];
+  const T q2 = M == 4 ? (T)qd[M == 4 ? 2 : 0] : T(0);
+  const T ir = rcp_nr(q0);
+  const T un = q1 * ir;
+  T ke;
+  if (M == 4) {
+    ke = fma(un, q1, (q2 * ir) * q2);
+  } else {
+    ke = un * q1;
+  }
+  const T p = gm1 * fma(T(-0.5), ke, E);
+  rec[Lo::Q0 * fs] = q0;
+  rec[Lo::Q1 * fs] = q1;
+  rec[Lo::E * fs] = E;
+  rec[Lo::F1 * fs] = fma(q1, un, p);
+  rec[Lo::F3 * fs] = (E + p) * un;
+  if (M == 4) {
+    rec[Lo::Q2 * fs] = q2;
+    rec[Lo::F2 * fs] = q2 * un;
+  }
+  rec[Lo::SR * fs] = sqrt(q0);
+}
+
+// Velocities and total enthalpy of one record (the Roe ingredients).
+template <class T, int M>
+__device__ __forceinline__ void roe_side(const T* __restrict__ rec, int fs, int o, T gm1, T& un, T& ut, T& H) {
+  typedef RecLayout<M> Lo;
+  const T q0 = rec[Lo::Q0 * fs + o], q1 = rec[Lo::Q1 * fs + o], E = rec[Lo::E * fs + o];
+  const T ir = rcp_nr(q0);
+  un = q1 * ir;
+  T ke;
+  if (M == 4) {
+    const T q2 = rec[(M == 4 ? Lo::Q2 : 0) * fs + o];
+    ut = q2 * ir;
+    ke = fma(un, q1, ut * q2);
+  } else {
+    ut = T(0);
+    ke = un * q1;
+  }
+  const T p = gm1 * fma(T(-0.5), ke, E);
+  H = (E + p) * ir;
+}
+
+// ---------------------------------------------------------------------------
+// Characteristic-wise WENO-ZA6 flux of the Euler equations at one interface
+// in the sweep-normal frame, from the records of its six-point stencil
+// (value of field f at stencil point j: rec[f * fs + off[j]]).  The y-sweep
+// builds its records in the permuted frame and permutes the result back; the
+// two tangential fields share one eigenvalue and one LF speed, so their order
+// does not change the reconstruction.
 //
 // Eigenvectors at the Roe average of cells i, i+1 (Section 4.2 uses the
 // characteristic-wise LF splitting; Roe's average defines the state):
@@ -137,84 +246,73 @@ __device__ __forceinline__ T split_pair(const T (&w)[6], const T (&g)[6], T a, c
 //   B = (u Q0 - Q1)/(2c), K = u Q1 + v Q2 - E, b1 = (gamma-1)/c^2,
 //   b2 = b1 q2  (the textbook left eigenvectors, factored).
 // ---------------------------------------------------------------------------
-template <class T, int M, bool GP>
-__device__ __forceinline__ void euler_flux(const double (&qs)[6][M], T gm1, const T (&alpha)[M],
-                                           const WeightCfg<T>& cfg, T (&Fh)[M]) {
-  // primitive variables and physical flux of the six cells (point values)
-  T Q[6][M], F[6][M], un[6], ut[6], pr[6];
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-#pragma unroll
-    for (int c = 0; c < M; ++c) Q[j][c] = (T)qs[j][c];
-    T ir = T(1) / Q[j][0];
-    un[j] = Q[j][1] * ir;
-    T ke;
-    if (M == 4) {
-      ut[j] = Q[j][2] * ir;
-      ke = un[j] * Q[j][1] + ut[j] * Q[j][2];
-    } else {
-      ut[j] = T(0);
-      ke = un[j] * Q[j][1];
-    }
-    pr[j] = gm1 * (Q[j][M - 1] - T(0.5) * ke);
-    F[j][0] = Q[j][1];
-    F[j][1] = Q[j][1] * un[j] + pr[j];
-    if (M == 4) F[j][2] = Q[j][2] * un[j];
-    F[j][M - 1] = (Q[j][M - 1] + pr[j]) * un[j];
-  }
+template <class T, int M, int WV>
+__device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, const int (&off)[6], T gm1,
+                                           const T (&alpha)[M], const WeightCfg<T>& cfg, T (&Fh)[M]) {
+  typedef RecLayout<M> Lo;
+#define ZA_R(f, j) rec[(f) * fs + off[j]]
   // Roe average of cells 2 (= i) and 3 (= i+1)
-  T sl = sqrt(Q[2][0]), sr = sqrt(Q[3][0]);
-  T iw = T(1) / (sl + sr);
-  T wl = sl * iw, wr = sr * iw;
-  T Hl = (Q[2][M - 1] + pr[2]) / Q[2][0], Hr = (Q[3][M - 1] + pr[3]) / Q[3][0];
-  T u = wl * un[2] + wr * un[3];
-  T v = (M == 4) ? wl * ut[2] + wr * ut[3] : T(0);
-  T H = wl * Hl + wr * Hr;
-  T q2 = T(0.5) * (u * u + v * v);
-  T c2 = gm1 * (H - q2);
-  T c = sqrt(c2);
-  T ic = T(1) / c;
-  T b1 = gm1 * (ic * ic);
-  T b2 = b1 * q2;
-  T hic = T(0.5) * ic;
+  const T sl = ZA_R(Lo::SR, 2), sr = ZA_R(Lo::SR, 3);
+  const T iw = rcp_nr(sl + sr);
+  const T wl = sl * iw, wr = sr * iw;
+  T unl, utl, Hl, unr, utr, Hr;
+  roe_side<T, M>(rec, fs, off[2], gm1, unl, utl, Hl);
+  roe_side<T, M>(rec, fs, off[3], gm1, unr, utr, Hr);
+  const T u = fma(wl, unl, wr * unr);
+  const T v = M == 4 ? fma(wl, utl, wr * utr) : T(0);
+  const T H = fma(wl, Hl, wr * Hr);
+  const T q2 = T(0.5) * fma(u, u, v * v);
+  const T c2 = gm1 * (H - q2);
+  const T c = sqrt(c2);
+  const T ic = rcp_nr(c);
+  const T b1 = gm1 * (ic * ic);
+  const T hb1 = T(0.5) * b1, hb2 = hb1 * q2;
+  const T hic = T(0.5) * ic;
   // project the stencil onto the characteristic fields
   T W[M][6], G[M][6];
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
+    const T Q0 = ZA_R(Lo::Q0, j), Q1 = ZA_R(Lo::Q1, j), E = ZA_R(Lo::E, j);
+    const T Q2 = M == 4 ? ZA_R(M == 4 ? Lo::Q2 : 0, j) : T(0);
+    const T F1 = ZA_R(Lo::F1, j), F3 = ZA_R(Lo::F3, j);
+    const T F2 = M == 4 ? ZA_R(M == 4 ? Lo::F2 : 0, j) : T(0);
     {
-      T K = u * Q[j][1] - Q[j][M - 1];
-      if (M == 4) K += v * Q[j][2];
-      T A = T(0.5) * (b2 * Q[j][0] - b1 * K);
-      T B = hic * (u * Q[j][0] - Q[j][1]);
+      T K = fma(u, Q1, -E);
+      if (M == 4) K = fma(v, Q2, K);
+      const T A = fma(hb2, Q0, -hb1 * K);
+      const T B = hic * fma(u, Q0, -Q1);
       W[0][j] = A + B;
-      W[1][j] = Q[j][0] - T(2) * A;
-      if (M == 4) W[2][j] = Q[j][2] - v * Q[j][0];
+      W[1][j] = fma(T(-2), A, Q0);
+      if (M == 4) W[2][j] = fma(-v, Q0, Q2);
       W[M - 1][j] = A - B;
     }
     {
-      T K = u * F[j][1] - F[j][M - 1];
-      if (M == 4) K += v * F[j][2];
-      T A = T(0.5) * (b2 * F[j][0] - b1 * K);
-      T B = hic * (u * F[j][0] - F[j][1]);
+      // physical flux (F0 = Q1, F1, [F2], F3)
+      T K = fma(u, F1, -F3);
+      if (M == 4) K = fma(v, F2, K);
+      const T A = fma(hb2, Q1, -hb1 * K);
+      const T B = hic * fma(u, Q1, -F1);
       G[0][j] = A + B;
-      G[1][j] = F[j][0] - T(2) * A;
-      if (M == 4) G[2][j] = F[j][2] - v * F[j][0];
+      G[1][j] = fma(T(-2), A, Q1);
+      if (M == 4) G[2][j] = fma(-v, Q1, F2);
       G[M - 1][j] = A - B;
     }
   }
+#undef ZA_R
   T gh[M];
 #pragma unroll
-  for (int s = 0; s < M; ++s) gh[s] = split_pair<T, GP>(W[s], G[s], alpha[s], cfg);
+  for (int s = 0; s < M; ++s) gh[s] = split_pair<T, WV>(W[s], G[s], alpha[s], cfg);
   // back-projection F = R g
-  T s03 = gh[0] + gh[M - 1], d30 = gh[M - 1] - gh[0];
-  T sum = s03 + gh[1];
+  const T s03 = gh[0] + gh[M - 1], d30 = gh[M - 1] - gh[0];
+  const T sum = s03 + gh[1];
+  const T uc = u * c;
   Fh[0] = sum;
-  Fh[1] = u * sum + c * d30;
+  Fh[1] = fma(u, sum, c * d30);
   if (M == 4) {
-    Fh[2] = v * sum + gh[2];
-    Fh[3] = H * s03 + (u * c) * d30 + q2 * gh[1] + v * gh[2];
+    Fh[2] = fma(v, sum, gh[2]);
+    Fh[3] = fma(H, s03, fma(uc, d30, fma(q2, gh[1], v * gh[2])));
   } else {
-    Fh[2] = H * s03 + (u * c) * d30 + q2 * gh[1];
+    Fh[2] = fma(H, s03, fma(uc, d30, q2 * gh[1]));
   }
 }
 

@@ -22,6 +22,7 @@ struct za_ctx {
   double* part = nullptr;    // reduction partials
   za::DevCtl* ctl = nullptr; // device control block
   int red_blocks = 1;
+  int ytile = 64;            // y-sweep rows per block
   int chunk_steps = 0;       // steps per host check in za_solve (0: default)
   bool timing = false;
   hipEvent_t ev_open[3] = {nullptr, nullptr, nullptr};

@@ -81,54 +81,67 @@ __device__ __forceinline__ double scalar_df(double u, double a) {
 }
 
 // ---------------------------------------------------------------------------
-// Interface flux of one sweep.  `base` points at component 0 of the line,
-// `cs` is the component stride (nx*ny), `ls` the stride along the line, n the
-// line length, k the interface (left face of cell k), bc the boundary rule.
-// DIR 1 permutes the 2D Euler state into the sweep-normal frame.
+// Records of one sweep direction (see za_device.hpp).  DIR 1 permutes the 2D
+// Euler state into the sweep-normal frame (rho, rho v, rho u, E).
 // ---------------------------------------------------------------------------
-template <int SYS, int M, int DIR, class T, bool GP>
-__device__ __forceinline__ void iface_flux(const double* __restrict__ base, size_t cs, size_t ls, int n,
-                                           int k, int bc, const Phys& ph, const DevCtl* ctl,
-                                           const WeightCfg<T>& cfg, T (&Fh)[M]) {
+template <int SYS, int M>
+struct NumFields { enum { value = (SYS == SYS_EULER) ? RecLayout<(M == 1 ? 4 : M)>::NF : 2 }; };
+
+// Gather cell `cell` (already boundary-mapped) of the line at `base` and build
+// its record at rec (field stride fs).
+template <int SYS, int M, int DIR, class T>
+__device__ __forceinline__ void stage_cell(const double* __restrict__ base, size_t cs, size_t off,
+                                           const Phys& ph, T* rec, int fs) {
   if (SYS == SYS_EULER) {
-    double qs[6][M];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const size_t off = (size_t)bc_map(k - 3 + j, n, bc) * ls;
-      if (M == 4 && DIR == 1) {
-        qs[j][0] = base[off];
-        qs[j][1] = base[off + 2 * cs];
-        qs[j][2] = base[off + cs];
-        qs[j][3] = base[off + 3 * cs];
-      } else {
-#pragma unroll
-        for (int c = 0; c < M; ++c) qs[j][c] = base[off + c * cs];
-      }
-    }
-    T al[M];
-    if (M == 4) {
-      al[0] = (T)ctl->alpha[DIR][0]; al[1] = (T)ctl->alpha[DIR][1];
-      al[2] = (T)ctl->alpha[DIR][2]; al[3] = (T)ctl->alpha[DIR][3];
-    } else {
-      al[0] = (T)ctl->alpha[0][0]; al[1] = (T)ctl->alpha[0][1]; al[M - 1] = (T)ctl->alpha[0][3];
-    }
-    T F[M];
-    euler_flux<T, M, GP>(qs, (T)ph.gm1, al, cfg, F);
+    double qd[M];
     if (M == 4 && DIR == 1) {
-      Fh[0] = F[0]; Fh[1] = F[2]; Fh[2] = F[1]; Fh[3] = F[3];
+      qd[0] = base[off];
+      qd[1] = base[off + 2 * cs];
+      qd[2] = base[off + cs];
+      qd[3] = base[off + 3 * cs];
+    } else {
+#pragma unroll
+      for (int c = 0; c < M; ++c) qd[c] = base[off + c * cs];
+    }
+    euler_record<T, (M == 1 ? 4 : M)>(*reinterpret_cast<const double(*)[(M == 1 ? 4 : M)]>(qd), (T)ph.gm1, rec, fs);
+  } else {
+    const T u = (T)base[off];
+    rec[0] = u;
+    rec[fs] = scalar_f<SYS, T>(u, (T)ph.adv[DIR]);
+  }
+}
+
+// Interface flux from the records of its six-point stencil; the result is
+// returned in the state's own component order.
+template <int SYS, int M, int DIR, class T, int WV>
+__device__ __forceinline__ void stencil_flux(const T* __restrict__ rec, int fs, const int (&off)[6],
+                                             const Phys& ph, const DevCtl* ctl, const WeightCfg<T>& cfg,
+                                             T (&Fh)[M]) {
+  if (SYS == SYS_EULER) {
+    constexpr int MM = (M == 1 ? 4 : M);
+    T al[MM];
+    if (MM == 4) {
+      al[0] = (T)ctl->alpha[DIR][0]; al[1] = (T)ctl->alpha[DIR][1];
+      al[2 % MM] = (T)ctl->alpha[DIR][2]; al[3 % MM] = (T)ctl->alpha[DIR][3];
+    } else {
+      al[0] = (T)ctl->alpha[0][0]; al[1] = (T)ctl->alpha[0][1]; al[MM - 1] = (T)ctl->alpha[0][3];
+    }
+    T F[MM];
+    euler_flux<T, MM, WV>(rec, fs, off, (T)ph.gm1, al, cfg, F);
+    if (MM == 4 && DIR == 1) {
+      Fh[0] = F[0]; Fh[1 % M] = F[2 % MM]; Fh[2 % M] = F[1]; Fh[3 % M] = F[3 % MM];
     } else {
 #pragma unroll
       for (int c = 0; c < M; ++c) Fh[c] = F[c];
     }
   } else {
     T w[6], g[6];
-    const T a = (T)ph.adv[DIR];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-      w[j] = (T)base[(size_t)bc_map(k - 3 + j, n, bc) * ls];
-      g[j] = scalar_f<SYS, T>(w[j], a);
+      w[j] = rec[off[j]];
+      g[j] = rec[fs + off[j]];
     }
-    Fh[0] = split_pair<T, GP>(w, g, (T)ctl->alpha[DIR][0], cfg);
+    Fh[0] = split_pair<T, WV>(w, g, (T)ctl->alpha[DIR][0], cfg);
   }
 }
 
@@ -142,22 +155,33 @@ struct SweepArgs {
   Phys ph;
   double ca, cb;         // stage: out = ca*qn + cb*(q + dt*L)
   int check_active;      // stepping: skip when the integration is inactive
+  int ytile;             // y-sweep rows per block (multiple of 4)
 };
 
 template <class T>
 struct CfgArg { WeightCfg<T> w; };
 
 // ---------------------------------------------------------------------------
-// x-sweep: one wavefront per line segment of 64 interfaces / 63 cells; each
-// lane computes one interface flux from its six-point stencil (coalesced,
-// shifted loads), the fluxes meet in LDS for the conservative difference.
-// Used for the 2D x-direction and for every 1D problem.
+// x-sweep: one wavefront per line segment of 64 interfaces / 63 cells.  The
+// wavefront first builds the records of its 69 cells (63 + the 6-cell halo,
+// coalesced loads) in LDS; each lane then computes one interface flux from
+// six consecutive records, and the fluxes meet in LDS again for the
+// conservative difference.  Used for the 2D x-direction and for 1D problems.
 // ---------------------------------------------------------------------------
 constexpr int XS_CELLS = 63;
+#ifndef ZA_XS_WAVES
+#define ZA_XS_WAVES 4   // minimum resident wavefronts per SIMD requested from the compiler
+#endif
+#ifndef ZA_YS_WAVES
+#define ZA_YS_WAVES 3
+#endif
+constexpr int XS_REC = 72;    // record slots per field and wavefront (69 used)
 
-template <int SYS, int M, class T, int MODE, bool GP>
-__global__ __launch_bounds__(256) void k_sweep_x(SweepArgs a, CfgArg<T> cfg) {
+template <int SYS, int M, class T, int MODE, int WV>
+__device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>& cfg) {
   if (a.check_active && !a.ctl->active) return;
+  constexpr int NF = NumFields<SYS, M>::value;
+  __shared__ T xr[4][NF * XS_REC];
   __shared__ double fl[4][M][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nx = a.g.nx, ny = a.g.ny;
@@ -169,9 +193,17 @@ __global__ __launch_bounds__(256) void k_sweep_x(SweepArgs a, CfgArg<T> cfg) {
   const int k = c0 + lane;
   const size_t cs = (size_t)nx * ny;
   const size_t row = (size_t)line * nx;
+  if (live) {
+    for (int idx = lane; idx < XS_CELLS + 6; idx += 64) {
+      const int j = bc_map(c0 - 3 + idx, nx, a.g.bc_x);
+      stage_cell<SYS, M, 0, T>(a.q + row, cs, (size_t)j, a.ph, &xr[wv][idx], XS_REC);
+    }
+  }
+  __syncthreads();
   if (live && k <= nx) {
     T F[M];
-    iface_flux<SYS, M, 0, T, GP>(a.q + row, cs, 1, nx, k, a.g.bc_x, a.ph, a.ctl, cfg.w, F);
+    const int off[6] = {lane, lane + 1, lane + 2, lane + 3, lane + 4, lane + 5};
+    stencil_flux<SYS, M, 0, T, WV>(&xr[wv][0], XS_REC, off, a.ph, a.ctl, cfg.w, F);
     if (MODE == MODE_FLUX) {
       if (lane < XS_CELLS || k == nx) {
 #pragma unroll
@@ -194,55 +226,136 @@ __global__ __launch_bounds__(256) void k_sweep_x(SweepArgs a, CfgArg<T> cfg) {
     if (MODE == MODE_RHS || MODE == MODE_LX) {
       a.out[o] = L;
     } else {  // MODE_STAGE (1D)
-      a.out[o] = a.ca * a.qn[o] + a.cb * (a.q[o] + a.ctl->dt * L);
+      a.out[o] = fma(a.ca, a.qn[o], a.cb * fma(a.ctl->dt, L, a.q[o]));
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// y-sweep (2D): lanes run along x (coalesced), each wavefront marches down a
-// run of YS_CELLS cells, keeping the previous interface flux in registers for
-// the conservative difference.  MODE_STAGE adds L_x and applies the stage.
+// y-sweep (2D): a block of four wavefronts owns 64 columns (one per lane,
+// coalesced) and a tile of a.ytile rows (chosen on the host so that one round
+// of resident blocks covers the grid), and marches down it four interface
+// rows at a time, one row per wavefront.  The records of the nine cell rows
+// the four stencils touch sit in an LDS ring; each iteration every
+// wavefront builds one new row (its global loads are issued an iteration
+// ahead), and the four interface fluxes meet in LDS for the conservative
+// difference, which MODE_STAGE combines with L_x into the RK3 stage.
 // ---------------------------------------------------------------------------
-constexpr int YS_CELLS = 16;
+constexpr int YS_TILE_MIN = 16;
+constexpr int YS_RING = 9;
 
-template <int SYS, int M, class T, int MODE, bool GP>
-__global__ __launch_bounds__(256) void k_sweep_y(SweepArgs a, CfgArg<T> cfg) {
+template <int SYS, int M, class T, int MODE, int WV>
+__device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>& cfg) {
   if (a.check_active && !a.ctl->active) return;
+  constexpr int NF = NumFields<SYS, M>::value;
+  __shared__ T ring[YS_RING * NF * 64];
+  __shared__ double fb[2][4][M][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nx = a.g.nx, ny = a.g.ny;
   const int x = blockIdx.x * 64 + lane;
-  const int y0 = (blockIdx.y * 4 + wv) * YS_CELLS;
-  if (x >= nx || y0 >= ny) return;
-  const int y1 = min(y0 + YS_CELLS, ny);
+  const bool xin = x < nx;
+  const int y0 = blockIdx.y * a.ytile;
+  const int ylast = min(y0 + a.ytile, ny);   // cells [y0, ylast)
+  const int kend = ylast;                    // interfaces y0 .. kend
   const size_t cs = (size_t)nx * ny;
-  const double* colq = a.q + x;
-  T prev[M];
-  for (int k = y0; k <= y1; ++k) {
+  const double* col = a.q + (xin ? x : 0);
+  auto slot = [&](int r) { return (r - y0 + 3) % YS_RING; };
+  auto stage_row = [&](int r) {
+    if (xin) {
+      const size_t off = (size_t)bc_map(r, ny, a.g.bc_y) * nx;
+      stage_cell<SYS, M, 1, T>(col, cs, off, a.ph, &ring[slot(r) * NF * 64 + lane], 64);
+    }
+  };
+  // rows y0-3 .. y0+5 for the first iteration
+  stage_row(y0 - 3 + wv);
+  stage_row(y0 + 1 + wv);
+  if (wv == 0) stage_row(y0 + 5);
+  __syncthreads();
+  const int nit = (kend - y0) / 4 + 1;
+  for (int it = 0; it < nit; ++it) {
+    const int k0 = y0 + 4 * it;
+    const int k = k0 + wv;
+    const bool act = k <= kend;
+    // prefetch the row this wavefront adds to the ring for the next iteration
+    const int rn = k0 + 6 + wv;
+    const bool need = rn <= kend + 2 && xin;
+    double qp[M];
+    if (need) {
+      const size_t off = (size_t)bc_map(rn, ny, a.g.bc_y) * nx;
+#pragma unroll
+      for (int c = 0; c < M; ++c) qp[c] = col[off + c * cs];
+    }
     T F[M];
-    iface_flux<SYS, M, 1, T, GP>(colq, cs, (size_t)nx, ny, k, a.g.bc_y, a.ph, a.ctl, cfg.w, F);
-    if (MODE == MODE_FLUX) {
-      if (k < y1 || k == ny) {
+    if (act && xin) {
+      int off[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) off[j] = slot(k - 3 + j) * NF * 64;
+      stencil_flux<SYS, M, 1, T, WV>(&ring[lane], 64, off, a.ph, a.ctl, cfg.w, F);
+#pragma unroll
+      for (int c = 0; c < M; ++c) fb[it & 1][wv][c][lane] = (double)F[c];
+      if (MODE == MODE_FLUX && (k < kend || k == ny)) {
 #pragma unroll
         for (int c = 0; c < M; ++c) a.out[(size_t)c * (ny + 1) * nx + (size_t)k * nx + x] = (double)F[c];
       }
-    } else if (k > y0) {
-      const size_t idx = (size_t)(k - 1) * nx + x;
+    }
+    __syncthreads();
+    const int r = k - 1;   // cell row finished by this wavefront
+    if (MODE != MODE_FLUX && act && xin && r >= y0 && r < ylast) {
+      const size_t idx = (size_t)r * nx + x;
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        const double L = -((double)F[c] - (double)prev[c]) * a.g.inv_dy;
+        const double fk = fb[it & 1][wv][c][lane];
+        const double fm = wv > 0 ? fb[it & 1][wv - 1][c][lane] : fb[(it - 1) & 1][3][c][lane];
+        const double L = -(fk - fm) * a.g.inv_dy;
         const size_t o = c * cs + idx;
         if (MODE == MODE_RHS) {
           a.out[o] = a.lx[o] + L;
         } else {  // MODE_STAGE
           const double Lt = a.lx[o] + L;
-          a.out[o] = a.ca * a.qn[o] + a.cb * (a.q[o] + a.ctl->dt * Lt);
+          a.out[o] = fma(a.ca, a.qn[o], a.cb * fma(a.ctl->dt, Lt, a.q[o]));
         }
       }
     }
+    if (need) {
+      // the slot of row rn held row rn - 9 = k0 - 3 + wv, read for the last
+      // time before the barrier above
+      T* rec = &ring[slot(rn) * NF * 64 + lane];
+      if (SYS == SYS_EULER) {
+        double qd[M];
+        if (M == 4) { qd[0] = qp[0]; qd[1] = qp[2 % M]; qd[2 % M] = qp[1]; qd[3 % M] = qp[3 % M]; }
+        else {
 #pragma unroll
-    for (int c = 0; c < M; ++c) prev[c] = F[c];
+          for (int c = 0; c < M; ++c) qd[c] = qp[c];
+        }
+        euler_record<T, (M == 1 ? 4 : M)>(*reinterpret_cast<const double(*)[(M == 1 ? 4 : M)]>(qd), (T)a.ph.gm1, rec, 64);
+      } else {
+        const T u = (T)qp[0];
+        rec[0] = u;
+        rec[64] = scalar_f<SYS, T>(u, (T)a.ph.adv[1]);
+      }
+    }
+    __syncthreads();
   }
+}
+
+// The fast variants (Z weights, p = 1, a stage or RHS mode) carry an
+// occupancy target; the others (general weights, flux output for checks)
+// let the compiler use as many registers as it likes.
+template <int SYS, int M, class T, int MODE, int WV>
+__global__ __launch_bounds__(256, ZA_XS_WAVES) void k_sweep_x(SweepArgs a, CfgArg<T> cfg) {
+  sweep_x_body<SYS, M, T, MODE, WV>(a, cfg);
+}
+template <int SYS, int M, class T, int MODE, int WV>
+__global__ __launch_bounds__(256) void k_sweep_x_any(SweepArgs a, CfgArg<T> cfg) {
+  sweep_x_body<SYS, M, T, MODE, WV>(a, cfg);
+}
+template <int SYS, int M, class T, int MODE, int WV>
+__global__ __launch_bounds__(256, ZA_YS_WAVES) void k_sweep_y(SweepArgs a, CfgArg<T> cfg) {
+  sweep_y_body<SYS, M, T, MODE, WV>(a, cfg);
+}
+template <int SYS, int M, class T, int MODE, int WV>
+__global__ __launch_bounds__(256) void k_sweep_y_any(SweepArgs a, CfgArg<T> cfg) {
+  sweep_y_body<SYS, M, T, MODE, WV>(a, cfg);
 }
 
 // ---------------------------------------------------------------------------

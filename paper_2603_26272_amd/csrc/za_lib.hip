@@ -97,8 +97,10 @@ static za_status hip_fail(za_ctx* c, hipError_t e, const char* what) {
 template <class T>
 static CfgArg<T> make_cfg(const za_problem& p) {
   CfgArg<T> c;
-  c.w.eps = (T)p.eps;
-  c.w.mu0 = (T)p.mu0;
+  // exact power-of-two rescalings of the reconstruction (see za6())
+  c.w.eps16 = (T)(16.0 * p.eps);
+  c.w.eps4 = (T)(4.0 * p.eps);
+  c.w.mu0x2 = (T)(2.0 * p.mu0);
   c.w.p = (T)p.p;
   c.w.ai = p.affine_invariant;
   c.w.linear = p.linear_weights;
@@ -120,49 +122,71 @@ static void timed_end(za_ctx* c, int cls) {
   c->events[cls].push_back({c->ev_open[cls], e});
 }
 
-template <int SYS, int M, class T, bool GP>
+template <int SYS, int M, class T, int WV>
 static void launch_x_t(za_ctx* c, int mode, const SweepArgs& a) {
   const CfgArg<T> cfg = make_cfg<T>(c->prob);
   const int nseg = (a.g.nx + XS_CELLS - 1) / XS_CELLS;
   const long long waves = (long long)a.g.ny * nseg;
-  const unsigned blocks = (unsigned)((waves + 3) / 4);
-  switch (mode) {
-    case MODE_FLUX: hipLaunchKernelGGL((k_sweep_x<SYS, M, T, MODE_FLUX, GP>), dim3(blocks), dim3(256), 0, c->stream, a, cfg); break;
-    case MODE_RHS: hipLaunchKernelGGL((k_sweep_x<SYS, M, T, MODE_RHS, GP>), dim3(blocks), dim3(256), 0, c->stream, a, cfg); break;
-    case MODE_LX: hipLaunchKernelGGL((k_sweep_x<SYS, M, T, MODE_LX, GP>), dim3(blocks), dim3(256), 0, c->stream, a, cfg); break;
-    default: hipLaunchKernelGGL((k_sweep_x<SYS, M, T, MODE_STAGE, GP>), dim3(blocks), dim3(256), 0, c->stream, a, cfg); break;
+  const dim3 grid((unsigned)((waves + 3) / 4)), blk(256);
+  if constexpr (WV == WV_Z1) {
+    switch (mode) {
+      case MODE_FLUX: hipLaunchKernelGGL((k_sweep_x_any<SYS, M, T, MODE_FLUX, WV>), grid, blk, 0, c->stream, a, cfg); break;
+      case MODE_RHS: hipLaunchKernelGGL((k_sweep_x<SYS, M, T, MODE_RHS, WV>), grid, blk, 0, c->stream, a, cfg); break;
+      case MODE_LX: hipLaunchKernelGGL((k_sweep_x<SYS, M, T, MODE_LX, WV>), grid, blk, 0, c->stream, a, cfg); break;
+      default: hipLaunchKernelGGL((k_sweep_x<SYS, M, T, MODE_STAGE, WV>), grid, blk, 0, c->stream, a, cfg); break;
+    }
+  } else {
+    switch (mode) {
+      case MODE_FLUX: hipLaunchKernelGGL((k_sweep_x_any<SYS, M, T, MODE_FLUX, WV>), grid, blk, 0, c->stream, a, cfg); break;
+      case MODE_RHS: hipLaunchKernelGGL((k_sweep_x_any<SYS, M, T, MODE_RHS, WV>), grid, blk, 0, c->stream, a, cfg); break;
+      case MODE_LX: hipLaunchKernelGGL((k_sweep_x_any<SYS, M, T, MODE_LX, WV>), grid, blk, 0, c->stream, a, cfg); break;
+      default: hipLaunchKernelGGL((k_sweep_x_any<SYS, M, T, MODE_STAGE, WV>), grid, blk, 0, c->stream, a, cfg); break;
+    }
   }
 }
 
-template <int SYS, int M, class T, bool GP>
+template <int SYS, int M, class T, int WV>
 static void launch_y_t(za_ctx* c, int mode, const SweepArgs& a) {
   const CfgArg<T> cfg = make_cfg<T>(c->prob);
-  const unsigned bx = (unsigned)((a.g.nx + 63) / 64);
-  const unsigned by = (unsigned)((a.g.ny + 4 * YS_CELLS - 1) / (4 * YS_CELLS));
-  switch (mode) {
-    case MODE_FLUX: hipLaunchKernelGGL((k_sweep_y<SYS, M, T, MODE_FLUX, GP>), dim3(bx, by), dim3(256), 0, c->stream, a, cfg); break;
-    case MODE_RHS: hipLaunchKernelGGL((k_sweep_y<SYS, M, T, MODE_RHS, GP>), dim3(bx, by), dim3(256), 0, c->stream, a, cfg); break;
-    default: hipLaunchKernelGGL((k_sweep_y<SYS, M, T, MODE_STAGE, GP>), dim3(bx, by), dim3(256), 0, c->stream, a, cfg); break;
+  const dim3 grid((unsigned)((a.g.nx + 63) / 64), (unsigned)((a.g.ny + a.ytile - 1) / a.ytile)), blk(256);
+  if constexpr (WV == WV_Z1) {
+    switch (mode) {
+      case MODE_FLUX: hipLaunchKernelGGL((k_sweep_y_any<SYS, M, T, MODE_FLUX, WV>), grid, blk, 0, c->stream, a, cfg); break;
+      case MODE_RHS: hipLaunchKernelGGL((k_sweep_y<SYS, M, T, MODE_RHS, WV>), grid, blk, 0, c->stream, a, cfg); break;
+      default: hipLaunchKernelGGL((k_sweep_y<SYS, M, T, MODE_STAGE, WV>), grid, blk, 0, c->stream, a, cfg); break;
+    }
+  } else {
+    switch (mode) {
+      case MODE_FLUX: hipLaunchKernelGGL((k_sweep_y_any<SYS, M, T, MODE_FLUX, WV>), grid, blk, 0, c->stream, a, cfg); break;
+      case MODE_RHS: hipLaunchKernelGGL((k_sweep_y_any<SYS, M, T, MODE_RHS, WV>), grid, blk, 0, c->stream, a, cfg); break;
+      default: hipLaunchKernelGGL((k_sweep_y_any<SYS, M, T, MODE_STAGE, WV>), grid, blk, 0, c->stream, a, cfg); break;
+    }
   }
 }
 
-// dispatch on (system, dim, precision, generic p)
+// Z weights with p = 1 and mu = 1 take the fast kernels; Ai, p != 1 and the
+// linear-weight test mode take the general ones.
+static bool general_weights(const za_problem& p) {
+  return p.p != 1.0 || p.affine_invariant || p.linear_weights;
+}
+
+// dispatch on (system, dim, precision, weight variant)
 template <int SYS, int M>
 static void launch_x_sys(za_ctx* c, int mode, const SweepArgs& a) {
-  const bool gp = c->prob.p != 1.0;
+  const bool gp = general_weights(c->prob);
   if (c->prob.precision == ZA_FP32_RECON) {
-    if (gp) launch_x_t<SYS, M, float, true>(c, mode, a); else launch_x_t<SYS, M, float, false>(c, mode, a);
+    if (gp) launch_x_t<SYS, M, float, WV_GENERAL>(c, mode, a); else launch_x_t<SYS, M, float, WV_Z1>(c, mode, a);
   } else {
-    if (gp) launch_x_t<SYS, M, double, true>(c, mode, a); else launch_x_t<SYS, M, double, false>(c, mode, a);
+    if (gp) launch_x_t<SYS, M, double, WV_GENERAL>(c, mode, a); else launch_x_t<SYS, M, double, WV_Z1>(c, mode, a);
   }
 }
 template <int SYS, int M>
 static void launch_y_sys(za_ctx* c, int mode, const SweepArgs& a) {
-  const bool gp = c->prob.p != 1.0;
+  const bool gp = general_weights(c->prob);
   if (c->prob.precision == ZA_FP32_RECON) {
-    if (gp) launch_y_t<SYS, M, float, true>(c, mode, a); else launch_y_t<SYS, M, float, false>(c, mode, a);
+    if (gp) launch_y_t<SYS, M, float, WV_GENERAL>(c, mode, a); else launch_y_t<SYS, M, float, WV_Z1>(c, mode, a);
   } else {
-    if (gp) launch_y_t<SYS, M, double, true>(c, mode, a); else launch_y_t<SYS, M, double, false>(c, mode, a);
+    if (gp) launch_y_t<SYS, M, double, WV_GENERAL>(c, mode, a); else launch_y_t<SYS, M, double, WV_Z1>(c, mode, a);
   }
 }
 
@@ -234,7 +258,31 @@ static SweepArgs base_args(za_ctx* c) {
   a.ctl = c->ctl;
   a.g = c->geom;
   a.ph = c->ph;
+  a.ytile = c->ytile;
   return a;
+}
+
+// Rows per y-sweep block: split each 64-column strip into as many tiles as
+// there are resident block slots per strip, so that one round of blocks
+// covers the grid (no tail round at partial occupancy).
+template <class T>
+static int pick_ytile(za_ctx* c) {
+  const za_problem& p = c->prob;
+  if (p.dim != 2) return 64;
+  int blocks_per_cu = 0, cus = 0;
+  const void* fn = p.system == ZA_EULER
+                       ? reinterpret_cast<const void*>(&k_sweep_y<SYS_EULER, 4, T, MODE_STAGE, WV_Z1>)
+                       : reinterpret_cast<const void*>(&k_sweep_y<SYS_ADV, 1, T, MODE_STAGE, WV_Z1>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, fn, 256, 0) != hipSuccess || blocks_per_cu < 1)
+    blocks_per_cu = 2;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
+    cus = 256;
+  const long long strips = (p.nx + 63) / 64;
+  const long long slots = (long long)blocks_per_cu * cus;
+  long long tiles = std::max<long long>(1, slots / strips);
+  int rows = (int)((p.ny + tiles - 1) / tiles);
+  rows = (rows + 3) / 4 * 4;
+  return std::max(rows, YS_TILE_MIN);
 }
 
 // One RK3 step on the stream (no host synchronisation).
@@ -313,6 +361,7 @@ za_status za_ctx_create(const za_problem* p, void* stream, za_ctx** out) {
   c->ph.dt_rule = p->dt_rule;
   c->ph.lf_scalar = p->lf == ZA_LF_SCALAR ? 1 : 0;
   c->red_blocks = (int)std::min<size_t>(RED_BLOCKS_MAX, std::max<size_t>(1, (ncell + 2047) / 2048));
+  c->ytile = p->precision == ZA_FP32_RECON ? pick_ytile<float>(c) : pick_ytile<double>(c);
   hipError_t e;
   void* ptr = nullptr;
   if ((e = hipMalloc(&ptr, st_bytes)) != hipSuccess) { delete c; return ZA_ERR_NOMEM; }
@@ -450,11 +499,18 @@ za_status za_solve(za_ctx* c, double* q, double t_final, int64_t max_steps, za_s
     const double tf = t_final > 0.0 ? t_final : std::numeric_limits<double>::infinity();
     hipLaunchKernelGGL(k_ctl_arm, dim3(1), dim3(64), 0, c->stream, c->ctl, 0.0, tf,
                        (long long)(max_steps > 0 ? max_steps : 0));
+    // A fixed step count is enqueued exactly; integrating to t_final
+    // enqueues chunks and lets the device retire the steps beyond t_final.
+    int64_t enqueued = 0;
     while (true) {
-      for (int s = 0; s < chunk; ++s)
+      int n = chunk;
+      if (t_final <= 0.0) n = (int)std::min<int64_t>(chunk, max_steps - enqueued);
+      for (int s = 0; s < n; ++s)
         if ((st = enqueue_step(c, q)) != ZA_OK) return st;
+      enqueued += n;
       if ((st = read_ctl(c, &h)) != ZA_OK) return st;
       if (!h.active || h.bad) break;
+      if (t_final <= 0.0 && enqueued >= max_steps) break;
     }
   }
   if (info) {
