@@ -23,6 +23,9 @@ struct za_ctx {
   za::DevCtl* ctl = nullptr; // device control block
   int red_blocks = 1;
   int ytile = 64;            // y-sweep rows per block
+  int stage_blocks = 1;      // blocks of the kernel that writes a stage state
+  int part_blocks = 1;       // capacity of `part` in blocks
+  bool speeds_valid = false; // part holds the wave speeds of the current q
   int chunk_steps = 0;       // steps per host check in za_solve (0: default)
   bool timing = false;
   hipEvent_t ev_open[3] = {nullptr, nullptr, nullptr};

@@ -81,6 +81,86 @@ __device__ __forceinline__ double scalar_df(double u, double a) {
 }
 
 // ---------------------------------------------------------------------------
+// Wave speeds: per block maxima of |u_n - c|, |u_n|, |u_n + c| per direction
+// (part[b][0..5] = ax0 ax1 ax3 ay0 ay1 ay3).  max(|u_n| + c) equals
+// max(|u_n - c|, |u_n + c|) exactly (c > 0; both round the same sum), so it
+// is not stored.  A non-finite or non-physical cell (rho <= 0, p <= 0) sets
+// slot 0 to +infinity, which the final reduction reports.  Maxima are exact
+// and order independent, so the result is deterministic.
+// ---------------------------------------------------------------------------
+constexpr int NPART = 6;
+constexpr int RED_BLOCKS_MAX = 1024;
+
+__device__ __forceinline__ double wave_max(double a, double b) { return a > b ? a : b; }
+
+template <int SYS, int M>
+__device__ __forceinline__ void cell_speeds(const double (&Q)[M], const Phys& ph, double (&r)[NPART]) {
+  if (SYS == SYS_EULER) {
+    const double rho = Q[0];
+    const double mx = Q[1 % M];
+    const double my = M == 4 ? Q[2 % M] : 0.0;
+    const double E = Q[M - 1];
+    const double ir = rcp_nr(rho);
+    const double u = mx * ir, v = my * ir;
+    const double p = ph.gm1 * fma(-0.5 * rho, fma(u, u, v * v), E);
+    const double c2 = ph.gamma * p * ir;
+    const bool ok = rho > 0.0 && p > 0.0 && c2 > 0.0 && (E - E) == 0.0 && (mx - mx) == 0.0 && (my - my) == 0.0;
+    if (!ok) { r[0] = __builtin_huge_val(); return; }
+    const double c = sqrt(c2);
+    r[0] = wave_max(r[0], fabs(u - c));
+    r[1] = wave_max(r[1], fabs(u));
+    r[2] = wave_max(r[2], fabs(u + c));
+    r[3] = wave_max(r[3], fabs(v - c));
+    r[4] = wave_max(r[4], fabs(v));
+    r[5] = wave_max(r[5], fabs(v + c));
+  } else {
+    const double u = Q[0];
+    if (!((u - u) == 0.0)) { r[0] = __builtin_huge_val(); return; }
+    const double ax = fabs(scalar_df<SYS>(u, ph.adv[0]));
+    const double ay = fabs(scalar_df<SYS>(u, ph.adv[1]));
+    r[0] = wave_max(r[0], ax); r[2] = r[0];
+    r[3] = wave_max(r[3], ay); r[5] = r[3];
+  }
+}
+
+// Block-wide maxima of r into dst[0..NPART); every thread of the block calls.
+__device__ __forceinline__ void block_max_store(double (&r)[NPART], double* __restrict__ dst) {
+#pragma unroll
+  for (int i = 0; i < NPART; ++i) {
+    for (int off = 32; off > 0; off >>= 1) r[i] = wave_max(r[i], __shfl_xor(r[i], off, 64));
+  }
+  __shared__ double sm[4][NPART];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NPART; ++i) sm[wv][i] = r[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < NPART) {
+    double v = sm[0][threadIdx.x];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = wave_max(v, sm[w][threadIdx.x]);
+    dst[threadIdx.x] = v;
+  }
+}
+
+template <int SYS, int M>
+__global__ __launch_bounds__(256) void k_wave_partial(const double* __restrict__ q, size_t ncell, Phys ph,
+                                                      const DevCtl* ctl, int check_active,
+                                                      double* __restrict__ part) {
+  if (check_active && !ctl->active) return;
+  double r[NPART];
+#pragma unroll
+  for (int i = 0; i < NPART; ++i) r[i] = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += (size_t)gridDim.x * blockDim.x) {
+    double Q[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) Q[c] = q[c * ncell + i];
+    cell_speeds<SYS, M>(Q, ph, r);
+  }
+  block_max_store(r, part + (size_t)blockIdx.x * NPART);
+}
+
+// ---------------------------------------------------------------------------
 // Records of one sweep direction (see za_device.hpp).  DIR 1 permutes the 2D
 // Euler state into the sweep-normal frame (rho, rho v, rho u, E).
 // ---------------------------------------------------------------------------
@@ -156,6 +236,7 @@ struct SweepArgs {
   double ca, cb;         // stage: out = ca*qn + cb*(q + dt*L)
   int check_active;      // stepping: skip when the integration is inactive
   int ytile;             // y-sweep rows per block (multiple of 4)
+  double* part;          // MODE_STAGE: per-block wave-speed maxima of the new state
 };
 
 template <class T>
@@ -217,18 +298,26 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
   if (MODE == MODE_FLUX) return;
   __syncthreads();
   const int i = c0 + lane;
-  if (!live || lane >= XS_CELLS || i >= nx) return;
-  const size_t idx = row + i;
+  double rs[NPART];
 #pragma unroll
-  for (int c = 0; c < M; ++c) {
-    const double L = -(fl[wv][c][lane + 1] - fl[wv][c][lane]) * a.g.inv_dx;
-    const size_t o = c * cs + idx;
-    if (MODE == MODE_RHS || MODE == MODE_LX) {
-      a.out[o] = L;
-    } else {  // MODE_STAGE (1D)
-      a.out[o] = fma(a.ca, a.qn[o], a.cb * fma(a.ctl->dt, L, a.q[o]));
+  for (int t = 0; t < NPART; ++t) rs[t] = 0.0;
+  if (live && lane < XS_CELLS && i < nx) {
+    const size_t idx = row + i;
+    double qnew[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      const double L = -(fl[wv][c][lane + 1] - fl[wv][c][lane]) * a.g.inv_dx;
+      const size_t o = c * cs + idx;
+      if (MODE == MODE_RHS || MODE == MODE_LX) {
+        a.out[o] = L;
+      } else {  // MODE_STAGE (1D)
+        qnew[c] = fma(a.ca, a.qn[o], a.cb * fma(a.ctl->dt, L, a.q[o]));
+        a.out[o] = qnew[c];
+      }
     }
+    if (MODE == MODE_STAGE) cell_speeds<SYS, M>(qnew, a.ph, rs);
   }
+  if (MODE == MODE_STAGE && a.part) block_max_store(rs, a.part + (size_t)blockIdx.x * NPART);
 }
 
 // ---------------------------------------------------------------------------
@@ -271,6 +360,9 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
   stage_row(y0 + 1 + wv);
   if (wv == 0) stage_row(y0 + 5);
   __syncthreads();
+  double rs[NPART];
+#pragma unroll
+  for (int t = 0; t < NPART; ++t) rs[t] = 0.0;
   const int nit = (kend - y0) / 4 + 1;
   for (int it = 0; it < nit; ++it) {
     const int k0 = y0 + 4 * it;
@@ -302,6 +394,7 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
     const int r = k - 1;   // cell row finished by this wavefront
     if (MODE != MODE_FLUX && act && xin && r >= y0 && r < ylast) {
       const size_t idx = (size_t)r * nx + x;
+      double qnew[M];
 #pragma unroll
       for (int c = 0; c < M; ++c) {
         const double fk = fb[it & 1][wv][c][lane];
@@ -312,9 +405,11 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
           a.out[o] = a.lx[o] + L;
         } else {  // MODE_STAGE
           const double Lt = a.lx[o] + L;
-          a.out[o] = fma(a.ca, a.qn[o], a.cb * fma(a.ctl->dt, Lt, a.q[o]));
+          qnew[c] = fma(a.ca, a.qn[o], a.cb * fma(a.ctl->dt, Lt, a.q[o]));
+          a.out[o] = qnew[c];
         }
       }
+      if (MODE == MODE_STAGE) cell_speeds<SYS, M>(qnew, a.ph, rs);
     }
     if (need) {
       // the slot of row rn held row rn - 9 = k0 - 3 + wv, read for the last
@@ -336,6 +431,8 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
     }
     __syncthreads();
   }
+  if (MODE == MODE_STAGE && a.part)
+    block_max_store(rs, a.part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NPART);
 }
 
 // The fast variants (Z weights, p = 1, a stage or RHS mode) carry an
@@ -358,73 +455,6 @@ __global__ __launch_bounds__(256) void k_sweep_y_any(SweepArgs a, CfgArg<T> cfg)
   sweep_y_body<SYS, M, T, MODE, WV>(a, cfg);
 }
 
-// ---------------------------------------------------------------------------
-// Wave speeds: per block maxima of |u_n - c|, |u_n|, |u_n + c| per direction,
-// max(|u_n| + c) per direction, and a non-finite / non-physical flag.
-// Maxima are exact and order independent, so the result is deterministic.
-// part[b][0..9]: ax0 ax1 ax3 ay0 ay1 ay3 sx sy bad
-// ---------------------------------------------------------------------------
-constexpr int NPART = 9;
-constexpr int RED_BLOCKS_MAX = 1024;
-
-__device__ __forceinline__ double wave_max(double a, double b) { return a > b ? a : b; }
-
-template <int SYS, int M>
-__global__ __launch_bounds__(256) void k_wave_partial(const double* __restrict__ q, size_t ncell, Phys ph,
-                                                      const DevCtl* ctl, int check_active,
-                                                      double* __restrict__ part) {
-  if (check_active && !ctl->active) return;
-  double r[NPART];
-#pragma unroll
-  for (int i = 0; i < NPART; ++i) r[i] = 0.0;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += (size_t)gridDim.x * blockDim.x) {
-    if (SYS == SYS_EULER) {
-      const double rho = q[i];
-      const double mx = q[ncell + i];
-      const double my = M == 4 ? q[2 * ncell + i] : 0.0;
-      const double E = q[(M - 1) * ncell + i];
-      const double u = mx / rho, v = my / rho;
-      const double p = ph.gm1 * (E - 0.5 * rho * (u * u + v * v));
-      const double c2 = ph.gamma * p / rho;
-      const bool ok = rho > 0.0 && p > 0.0 && c2 > 0.0 && (E - E) == 0.0 && (mx - mx) == 0.0 && (my - my) == 0.0;
-      if (!ok) { r[8] = 1.0; continue; }
-      const double c = sqrt(c2);
-      r[0] = wave_max(r[0], fabs(u - c));
-      r[1] = wave_max(r[1], fabs(u));
-      r[2] = wave_max(r[2], fabs(u + c));
-      r[3] = wave_max(r[3], fabs(v - c));
-      r[4] = wave_max(r[4], fabs(v));
-      r[5] = wave_max(r[5], fabs(v + c));
-      r[6] = wave_max(r[6], fabs(u) + c);
-      r[7] = wave_max(r[7], fabs(v) + c);
-    } else {
-      const double u = q[i];
-      if (!((u - u) == 0.0)) { r[8] = 1.0; continue; }
-      const double ax = fabs(scalar_df<SYS>(u, ph.adv[0]));
-      const double ay = fabs(scalar_df<SYS>(u, ph.adv[1]));
-      r[0] = wave_max(r[0], ax); r[6] = r[0];
-      r[3] = wave_max(r[3], ay); r[7] = r[3];
-    }
-  }
-  // wavefront then block reduction
-#pragma unroll
-  for (int i = 0; i < NPART; ++i) {
-    for (int off = 32; off > 0; off >>= 1) r[i] = wave_max(r[i], __shfl_xor(r[i], off, 64));
-  }
-  __shared__ double sm[4][NPART];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NPART; ++i) sm[wv][i] = r[i];
-  }
-  __syncthreads();
-  if (threadIdx.x < NPART) {
-    double v = sm[0][threadIdx.x];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = wave_max(v, sm[w][threadIdx.x]);
-    part[(size_t)blockIdx.x * NPART + threadIdx.x] = v;
-  }
-}
-
 enum FinalKind { FIN_RHS = 0, FIN_STAGE0 = 1, FIN_STAGEK = 2 };
 
 template <int M>
@@ -443,10 +473,11 @@ __global__ __launch_bounds__(64) void k_wave_final(const double* __restrict__ pa
   }
   if (threadIdx.x != 0) return;
   if (kind != FIN_RHS && !ctl->active) return;
-  const bool bad = r[8] != 0.0;
+  const bool bad = !(r[0] < __builtin_huge_val());
+  const double sx = wave_max(r[0], r[2]), sy = wave_max(r[3], r[5]);
   if (is_euler) {
     if (ph.lf_scalar) {
-      for (int s = 0; s < 4; ++s) { ctl->alpha[0][s] = r[6]; ctl->alpha[1][s] = r[7]; }
+      for (int s = 0; s < 4; ++s) { ctl->alpha[0][s] = sx; ctl->alpha[1][s] = sy; }
     } else {
       ctl->alpha[0][0] = r[0]; ctl->alpha[0][1] = r[1]; ctl->alpha[0][2] = r[1]; ctl->alpha[0][3] = r[2];
       ctl->alpha[1][0] = r[3]; ctl->alpha[1][1] = r[4]; ctl->alpha[1][2] = r[4]; ctl->alpha[1][3] = r[5];
@@ -455,8 +486,8 @@ __global__ __launch_bounds__(64) void k_wave_final(const double* __restrict__ pa
     ctl->alpha[0][0] = r[0];
     ctl->alpha[1][0] = r[3];
   }
-  ctl->smax[0] = r[6];
-  ctl->smax[1] = r[7];
+  ctl->smax[0] = sx;
+  ctl->smax[1] = sy;
   if (bad) {
     if (!ctl->bad) ctl->bad_step = ctl->steps;
     ctl->bad = 1;
@@ -473,9 +504,9 @@ __global__ __launch_bounds__(64) void k_wave_final(const double* __restrict__ pa
       const double h = dim == 2 ? fmin(g.dx, g.dy) : g.dx;
       dt = ph.cfl * h * h;
     } else if (dim == 1) {
-      dt = ph.cfl * g.dx / r[6];
+      dt = ph.cfl * g.dx / sx;
     } else {
-      dt = ph.cfl / (r[6] / g.dx + r[7] / g.dy);
+      dt = ph.cfl / (sx / g.dx + sy / g.dy);
     }
     ctl->last = 0;
     if (ctl->t + dt >= ctl->t_final) { dt = ctl->t_final - ctl->t; ctl->last = 1; }

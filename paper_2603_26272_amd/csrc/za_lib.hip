@@ -68,7 +68,11 @@ size_t za_workspace_bytes(const za_problem* p) {
   const size_t st = za_state_count(p) * sizeof(double);
   size_t b = 2 * st;                      // Q1, Q2
   if (p->dim == 2) b += st;               // L_x
-  b += (size_t)RED_BLOCKS_MAX * NPART * sizeof(double) + 4096 + sizeof(DevCtl);
+  // reduction partials: at most one per stage-kernel block (bounded by the
+  // grid), at least RED_BLOCKS_MAX
+  const size_t blocks = p->dim == 2 ? (size_t)((p->nx + 63) / 64) * (size_t)((p->ny + 15) / 16)
+                                    : (size_t)(((p->nx + XS_CELLS - 1) / XS_CELLS + 3) / 4);
+  b += std::max<size_t>(RED_BLOCKS_MAX, blocks) * NPART * sizeof(double) + 4096 + sizeof(DevCtl);
   return b;
 }
 
@@ -214,6 +218,12 @@ static void launch_y(za_ctx* c, int mode, const SweepArgs& a) {
   timed_end(c, 1);
 }
 
+static void launch_final(za_ctx* c, int kind, int nblk) {
+  hipLaunchKernelGGL((k_wave_final<4>), dim3(1), dim3(64), 0, c->stream, c->part, nblk, c->ctl, c->geom, c->ph,
+                     c->prob.dim, kind, c->prob.system == ZA_EULER ? 1 : 0);
+}
+
+// Stand-alone wave-speed reduction of q followed by the final reduction.
 static void launch_wave(za_ctx* c, const double* q, int kind, int check_active) {
   timed_begin(c, 2);
   const size_t ncell = (size_t)c->prob.nx * c->prob.ny;
@@ -235,8 +245,7 @@ static void launch_wave(za_ctx* c, const double* q, int kind, int check_active) 
       hipLaunchKernelGGL((k_wave_partial<SYS_BUCKLEY, 1>), dim3(nblk), dim3(256), 0, c->stream, q, ncell, c->ph, c->ctl, check_active, c->part);
       break;
   }
-  hipLaunchKernelGGL((k_wave_final<4>), dim3(1), dim3(64), 0, c->stream, c->part, nblk, c->ctl, c->geom, c->ph,
-                     c->prob.dim, kind, c->prob.system == ZA_EULER ? 1 : 0);
+  launch_final(c, kind, nblk);
   timed_end(c, 2);
 }
 
@@ -259,6 +268,7 @@ static SweepArgs base_args(za_ctx* c) {
   a.g = c->geom;
   a.ph = c->ph;
   a.ytile = c->ytile;
+  a.part = nullptr;
   return a;
 }
 
@@ -285,20 +295,29 @@ static int pick_ytile(za_ctx* c) {
   return std::max(rows, YS_TILE_MIN);
 }
 
-// One RK3 step on the stream (no host synchronisation).
+// One RK3 step on the stream (no host synchronisation).  The kernel that
+// writes a stage's new state also leaves the per-block wave-speed maxima of
+// that state in c->part, so only the first step of an API call needs a
+// stand-alone reduction pass.
 static za_status enqueue_step(za_ctx* c, double* q) {
   const double ca[3] = {0.0, 0.75, 1.0 / 3.0};
   const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
   const double* in[3] = {q, c->q1, c->q2};
   double* out[3] = {c->q1, c->q2, q};
   for (int s = 0; s < 3; ++s) {
-    launch_wave(c, in[s], s == 0 ? FIN_STAGE0 : FIN_STAGEK, 1);
+    const int kind = s == 0 ? FIN_STAGE0 : FIN_STAGEK;
+    if (s == 0 && !c->speeds_valid) {
+      launch_wave(c, in[s], kind, 1);
+    } else {
+      launch_final(c, kind, c->stage_blocks);
+    }
     SweepArgs a = base_args(c);
     a.check_active = 1;
     a.q = in[s];
     a.qn = q;
     a.ca = ca[s];
     a.cb = cb[s];
+    a.part = c->part;
     if (c->prob.dim == 1) {
       a.out = out[s];
       launch_x(c, MODE_STAGE, a);
@@ -311,6 +330,7 @@ static za_status enqueue_step(za_ctx* c, double* q) {
     }
   }
   hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, c->stream, c->ctl);
+  c->speeds_valid = true;
   ZA_CHECK_LAUNCH(c, "step launch");
   return ZA_OK;
 }
@@ -362,6 +382,13 @@ za_status za_ctx_create(const za_problem* p, void* stream, za_ctx** out) {
   c->ph.lf_scalar = p->lf == ZA_LF_SCALAR ? 1 : 0;
   c->red_blocks = (int)std::min<size_t>(RED_BLOCKS_MAX, std::max<size_t>(1, (ncell + 2047) / 2048));
   c->ytile = p->precision == ZA_FP32_RECON ? pick_ytile<float>(c) : pick_ytile<double>(c);
+  if (p->dim == 2) {
+    c->stage_blocks = ((p->nx + 63) / 64) * ((p->ny + c->ytile - 1) / c->ytile);
+  } else {
+    const long long nseg = (p->nx + XS_CELLS - 1) / XS_CELLS;
+    c->stage_blocks = (int)((nseg * p->ny + 3) / 4);
+  }
+  c->part_blocks = std::max(RED_BLOCKS_MAX, c->stage_blocks);
   hipError_t e;
   void* ptr = nullptr;
   if ((e = hipMalloc(&ptr, st_bytes)) != hipSuccess) { delete c; return ZA_ERR_NOMEM; }
@@ -372,7 +399,7 @@ za_status za_ctx_create(const za_problem* p, void* stream, za_ctx** out) {
     if ((e = hipMalloc(&ptr, st_bytes)) != hipSuccess) { za_ctx_destroy(c); return ZA_ERR_NOMEM; }
     c->lx = (double*)ptr;
   }
-  if ((e = hipMalloc(&ptr, (size_t)RED_BLOCKS_MAX * NPART * sizeof(double) + 4096)) != hipSuccess) {
+  if ((e = hipMalloc(&ptr, (size_t)c->part_blocks * NPART * sizeof(double) + 4096)) != hipSuccess) {
     za_ctx_destroy(c);
     return ZA_ERR_NOMEM;
   }
@@ -408,6 +435,7 @@ za_status za_ctx_set_stream(za_ctx* c, void* stream) {
 
 za_status za_rhs(za_ctx* c, const double* q, double* rhs) {
   if (!c || !q || !rhs || q == rhs) return ZA_ERR_ARG;
+  c->speeds_valid = false;
   launch_wave(c, q, FIN_RHS, 0);
   SweepArgs a = base_args(c);
   a.q = q;
@@ -423,6 +451,7 @@ za_status za_rhs(za_ctx* c, const double* q, double* rhs) {
 
 za_status za_rhs_fluxes(za_ctx* c, const double* q, double* fx, double* fy) {
   if (!c || !q || !fx) return ZA_ERR_ARG;
+  c->speeds_valid = false;
   launch_wave(c, q, FIN_RHS, 0);
   SweepArgs a = base_args(c);
   a.q = q;
@@ -446,6 +475,7 @@ static za_status read_ctl(za_ctx* c, DevCtl* h) {
 
 za_status za_step(za_ctx* c, double* q, double dt, double* dt_used) {
   if (!c || !q) return ZA_ERR_ARG;
+  c->speeds_valid = false;
   if (!(dt > 0.0) && !(dt <= 0.0)) return ZA_ERR_ARG;  // NaN
   hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, c->stream, c->ctl, fresh_ctl());
   hipLaunchKernelGGL(k_ctl_arm, dim3(1), dim3(64), 0, c->stream, c->ctl, dt > 0.0 ? dt : 0.0,
@@ -463,6 +493,7 @@ za_status za_step(za_ctx* c, double* q, double dt, double* dt_used) {
 
 za_status za_solve(za_ctx* c, double* q, double t_final, int64_t max_steps, za_solve_info* info) {
   if (!c || !q) return ZA_ERR_ARG;
+  c->speeds_valid = false;
   if (!(t_final > 0.0) && max_steps <= 0) return ZA_ERR_ARG;
   if (t_final != t_final) return ZA_ERR_ARG;
   const auto& p = c->prob;
@@ -525,8 +556,9 @@ za_status za_solve(za_ctx* c, double* q, double t_final, int64_t max_steps, za_s
 
 za_status za_conserved_sums(za_ctx* c, const double* q, double* sums) {
   if (!c || !q || !sums) return ZA_ERR_ARG;
+  c->speeds_valid = false;
   const size_t ncell = (size_t)c->prob.nx * c->prob.ny;
-  const int nblk = (int)std::min<size_t>(RED_BLOCKS_MAX * NPART, std::max<size_t>(1, (ncell + 4095) / 4096));
+  const int nblk = (int)std::min<size_t>((size_t)c->part_blocks * NPART, std::max<size_t>(1, (ncell + 4095) / 4096));
   const size_t chunk = (ncell + nblk - 1) / nblk;
   std::vector<double> part(nblk);
   for (int comp = 0; comp < c->m; ++comp) {

@@ -209,7 +209,7 @@ def test_step_cfl_dt_and_state(dev):
     with Ctx(P) as ctx:
         dt = ctx.step(q, 0.0, sync=True)
     ref, dt_ref, st = orc.step(P, q0, 0.0)
-    assert abs(dt - dt_ref) <= 4e-16 * dt_ref
+    assert abs(dt - dt_ref) <= 1e-15 * dt_ref  # wave speeds via a Newton reciprocal: a few ulp
     assert_close(q.cpu().numpy(), ref, 1e-10, "step")
 
 
