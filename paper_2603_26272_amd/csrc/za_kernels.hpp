@@ -259,7 +259,7 @@ constexpr int XS_CELLS = 63;
 constexpr int XS_REC = 72;    // record slots per field and wavefront (69 used)
 
 template <int SYS, int M, class T, int MODE, int WV>
-__device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>& cfg) {
+__device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>& cfg, int bid) {
   if (a.check_active && !a.ctl->active) return;
   constexpr int NF = NumFields<SYS, M>::value;
   __shared__ T xr[4][NF * XS_REC];
@@ -267,7 +267,7 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nx = a.g.nx, ny = a.g.ny;
   const int nseg = (nx + XS_CELLS - 1) / XS_CELLS;
-  const long long wid = (long long)blockIdx.x * 4 + wv;
+  const long long wid = (long long)bid * 4 + wv;
   const int line = (int)(wid / nseg), seg = (int)(wid % nseg);
   const bool live = line < ny;
   const int c0 = seg * XS_CELLS;
@@ -317,7 +317,7 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
     }
     if (MODE == MODE_STAGE) cell_speeds<SYS, M>(qnew, a.ph, rs);
   }
-  if (MODE == MODE_STAGE && a.part) block_max_store(rs, a.part + (size_t)blockIdx.x * NPART);
+  if (MODE == MODE_STAGE && a.part) block_max_store(rs, a.part + (size_t)bid * NPART);
 }
 
 // ---------------------------------------------------------------------------
@@ -334,16 +334,16 @@ constexpr int YS_TILE_MIN = 16;
 constexpr int YS_RING = 9;
 
 template <int SYS, int M, class T, int MODE, int WV>
-__device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>& cfg) {
+__device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>& cfg, int bx, int by, int gx) {
   if (a.check_active && !a.ctl->active) return;
   constexpr int NF = NumFields<SYS, M>::value;
   __shared__ T ring[YS_RING * NF * 64];
   __shared__ double fb[2][4][M][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nx = a.g.nx, ny = a.g.ny;
-  const int x = blockIdx.x * 64 + lane;
+  const int x = bx * 64 + lane;
   const bool xin = x < nx;
-  const int y0 = blockIdx.y * a.ytile;
+  const int y0 = by * a.ytile;
   const int ylast = min(y0 + a.ytile, ny);   // cells [y0, ylast)
   const int kend = ylast;                    // interfaces y0 .. kend
   const size_t cs = (size_t)nx * ny;
@@ -432,7 +432,7 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
     __syncthreads();
   }
   if (MODE == MODE_STAGE && a.part)
-    block_max_store(rs, a.part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NPART);
+    block_max_store(rs, a.part + ((size_t)by * gx + bx) * NPART);
 }
 
 // The fast variants (Z weights, p = 1, a stage or RHS mode) carry an
@@ -440,26 +440,25 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
 // let the compiler use as many registers as it likes.
 template <int SYS, int M, class T, int MODE, int WV>
 __global__ __launch_bounds__(256, ZA_XS_WAVES) void k_sweep_x(SweepArgs a, CfgArg<T> cfg) {
-  sweep_x_body<SYS, M, T, MODE, WV>(a, cfg);
+  sweep_x_body<SYS, M, T, MODE, WV>(a, cfg, blockIdx.x);
 }
 template <int SYS, int M, class T, int MODE, int WV>
 __global__ __launch_bounds__(256) void k_sweep_x_any(SweepArgs a, CfgArg<T> cfg) {
-  sweep_x_body<SYS, M, T, MODE, WV>(a, cfg);
+  sweep_x_body<SYS, M, T, MODE, WV>(a, cfg, blockIdx.x);
 }
 template <int SYS, int M, class T, int MODE, int WV>
 __global__ __launch_bounds__(256, ZA_YS_WAVES) void k_sweep_y(SweepArgs a, CfgArg<T> cfg) {
-  sweep_y_body<SYS, M, T, MODE, WV>(a, cfg);
+  sweep_y_body<SYS, M, T, MODE, WV>(a, cfg, blockIdx.x, blockIdx.y, gridDim.x);
 }
 template <int SYS, int M, class T, int MODE, int WV>
 __global__ __launch_bounds__(256) void k_sweep_y_any(SweepArgs a, CfgArg<T> cfg) {
-  sweep_y_body<SYS, M, T, MODE, WV>(a, cfg);
+  sweep_y_body<SYS, M, T, MODE, WV>(a, cfg, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 enum FinalKind { FIN_RHS = 0, FIN_STAGE0 = 1, FIN_STAGEK = 2 };
 
-template <int M>
-__global__ __launch_bounds__(64) void k_wave_final(const double* __restrict__ part, int nblk, DevCtl* ctl,
-                                                   Geom g, Phys ph, int dim, int kind, int is_euler) {
+__device__ __forceinline__ void wave_final_body(const double* __restrict__ part, int nblk, DevCtl* ctl,
+                                                const Geom& g, const Phys& ph, int dim, int kind, int is_euler) {
   double r[NPART];
 #pragma unroll
   for (int i = 0; i < NPART; ++i) r[i] = 0.0;
@@ -514,7 +513,13 @@ __global__ __launch_bounds__(64) void k_wave_final(const double* __restrict__ pa
   }
 }
 
-__global__ void k_step_end(DevCtl* ctl) {
+template <int M>
+__global__ __launch_bounds__(64) void k_wave_final(const double* __restrict__ part, int nblk, DevCtl* ctl,
+                                                   Geom g, Phys ph, int dim, int kind, int is_euler) {
+  wave_final_body(part, nblk, ctl, g, ph, dim, kind, is_euler);
+}
+
+__device__ __forceinline__ void step_end_body(DevCtl* ctl) {
   if (threadIdx.x != 0 || !ctl->active) return;
   const double dt = ctl->dt;
   ctl->t = ctl->last ? ctl->t_final : ctl->t + dt;
@@ -525,9 +530,11 @@ __global__ void k_step_end(DevCtl* ctl) {
   if (ctl->max_steps > 0 && ctl->steps >= ctl->max_steps) ctl->active = 0;
 }
 
+static __global__ void k_step_end(DevCtl* ctl) { step_end_body(ctl); }
+
 // Fixed-order FP64 sums of each component (deterministic for a given size):
 // block b sums the contiguous chunk [b*chunk, (b+1)*chunk) with a fixed tree.
-__global__ __launch_bounds__(256) void k_sum_partial(const double* __restrict__ q, size_t n, size_t chunk,
+static __global__ __launch_bounds__(256) void k_sum_partial(const double* __restrict__ q, size_t n, size_t chunk,
                                                      double* __restrict__ part) {
   const size_t lo = (size_t)blockIdx.x * chunk;
   const size_t hi = lo + chunk < n ? lo + chunk : n;

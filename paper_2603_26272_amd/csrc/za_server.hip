@@ -1,17 +1,575 @@
-// Serving entry points (continuous batching); filled in by the scheduler.
+// Continuous-batching server of libza (the za_server_* calls of za.h).
+//
+// Requests (1D or 2D Euler solves of any size, FP64 or FP32 reconstruction)
+// are admitted while a slot is free and their device footprint fits the HBM
+// budget, which is one pre-allocated pool sub-allocated first-fit.  Each
+// scheduler step advances every admitted request by one SSP-RK3 step: per
+// class (dim x precision) one launch per kernel of the step covers the
+// blocks of all the class's requests, and each block finds its request in a
+// device slot table by binary search over prefix block offsets.  The step of
+// a class is a hipGraph captured once per grid capacity (power-of-two block
+// counts; surplus blocks exit at once), so admitting or retiring requests
+// only rewrites the table.  Classes run on separate streams and overlap.
+// Every request keeps its own Lax-Friedrichs speeds, dt and step count, and
+// its arithmetic does not depend on the rest of the batch, so a result is
+// the same bit for bit alone and in a mix.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <limits>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
 #include "za.h"
+#include "za_internal.hpp"
+#include "za_kernels.hpp"
+
+namespace zs {
+using namespace za;
+
+constexpr int MAX_SLOTS = 256;  // per class
+constexpr int NCLASS = 4;       // (1D, 2D) x (FP64, FP32 reconstruction)
+constexpr int SERVE_YTILE = 32; // y-sweep rows per block in batches
+
+struct SlotDesc {
+  double* st;        // the request's state (Q^n, then the result)
+  double* q1;        // RK3 stage states
+  double* q2;
+  double* lx;        // 2D: x-sweep partial RHS
+  double* part;      // wave-speed maxima per stage-kernel block
+  DevCtl* ctl;       // the request's control block
+  Geom g;
+  Phys ph;
+  double eps16, eps4, mu0x2;
+  int xblocks;       // x-sweep blocks
+  int ystrips;       // y-sweep: 64-column strips
+  int yblocks;       // y-sweep blocks (strips x tiles)
+  int stage_blocks;  // blocks of the kernel that writes a stage state
+};
+
+struct BatchTable {
+  int n, xtot, ytot, pad;
+  int xoff[MAX_SLOTS + 1];
+  int yoff[MAX_SLOTS + 1];
+  SlotDesc s[MAX_SLOTS];
+};
+
+__device__ __forceinline__ int find_slot(const int* __restrict__ off, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ SweepArgs slot_args(const SlotDesc& d, int stage, bool lx_out) {
+  SweepArgs a;
+  a.q = stage == 0 ? d.st : (stage == 1 ? d.q1 : d.q2);
+  a.qn = d.st;
+  a.lx = d.lx;
+  a.out = lx_out ? d.lx : (stage == 0 ? d.q1 : (stage == 1 ? d.q2 : d.st));
+  a.ctl = d.ctl;
+  a.g = d.g;
+  a.ph = d.ph;
+  a.ca = stage == 0 ? 0.0 : (stage == 1 ? 0.75 : 1.0 / 3.0);
+  a.cb = stage == 0 ? 1.0 : (stage == 1 ? 0.25 : 2.0 / 3.0);
+  a.check_active = 1;
+  a.ytile = SERVE_YTILE;
+  a.part = d.part;
+  return a;
+}
+
+template <class T>
+__device__ __forceinline__ CfgArg<T> slot_cfg(const SlotDesc& d) {
+  CfgArg<T> c;
+  c.w.eps16 = (T)d.eps16;
+  c.w.eps4 = (T)d.eps4;
+  c.w.mu0x2 = (T)d.mu0x2;
+  c.w.p = T(1);
+  c.w.ai = 0;
+  c.w.linear = 0;
+  return c;
+}
+
+template <int M, class T>
+__global__ __launch_bounds__(256, ZA_XS_WAVES) void kb_sweep_x(const BatchTable* __restrict__ tab, int stage) {
+  const int b = blockIdx.x;
+  if (b >= tab->xtot) return;
+  const int s = find_slot(tab->xoff, tab->n, b);
+  const SlotDesc& d = tab->s[s];
+  const SweepArgs a = slot_args(d, stage, M == 4);
+  const CfgArg<T> cfg = slot_cfg<T>(d);
+  if (M == 4)
+    sweep_x_body<SYS_EULER, M, T, MODE_LX, WV_Z1>(a, cfg, b - tab->xoff[s]);
+  else
+    sweep_x_body<SYS_EULER, M, T, MODE_STAGE, WV_Z1>(a, cfg, b - tab->xoff[s]);
+}
+
+template <class T>
+__global__ __launch_bounds__(256, ZA_YS_WAVES) void kb_sweep_y(const BatchTable* __restrict__ tab, int stage) {
+  const int b = blockIdx.x;
+  if (b >= tab->ytot) return;
+  const int s = find_slot(tab->yoff, tab->n, b);
+  const SlotDesc& d = tab->s[s];
+  const SweepArgs a = slot_args(d, stage, false);
+  const CfgArg<T> cfg = slot_cfg<T>(d);
+  const int local = b - tab->yoff[s];
+  sweep_y_body<SYS_EULER, 4, T, MODE_STAGE, WV_Z1>(a, cfg, local % d.ystrips, local / d.ystrips, d.ystrips);
+}
+
+__global__ __launch_bounds__(64) void kb_final(const BatchTable* __restrict__ tab, int kind, int dim) {
+  const int s = blockIdx.x;
+  if (s >= tab->n) return;
+  const SlotDesc& d = tab->s[s];
+  wave_final_body(d.part, d.stage_blocks, d.ctl, d.g, d.ph, dim, kind, 1);
+}
+
+__global__ __launch_bounds__(64) void kb_step_end(const BatchTable* __restrict__ tab) {
+  const int s = blockIdx.x;
+  if (s >= tab->n) return;
+  step_end_body(tab->s[s].ctl);
+}
+
+__global__ void k_ctl_set(DevCtl* ctl, DevCtl v) {
+  if (threadIdx.x == 0) *ctl = v;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Pool {  // first-fit sub-allocation of [0, cap), 256-byte granules
+  std::map<size_t, size_t> free_;
+  void init(size_t cap) { free_.clear(); free_[0] = cap; }
+  bool alloc(size_t n, size_t* off) {
+    n = (n + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *off = it->first;
+        const size_t rest = it->second - n, base = it->first + n;
+        free_.erase(it);
+        if (rest) free_[base] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = (n + 255) & ~size_t(255);
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct Req {
+  za_req_id id = 0;
+  za_problem prob;
+  int cls = 0, m = 1;
+  size_t ncell = 0;
+  std::vector<double> q0, qout;
+  int64_t n_steps = 0;
+  int64_t t_arr = 0, t_adm = 0, t_fin = 0;
+  int status = ZA_OK;
+  bool admitted = false, done = false;
+  int slot = -1;           // fixed control-block index in its class
+  size_t off = 0, bytes = 0;
+  SlotDesc desc;
+  int64_t steps = 0, interfaces = 0;
+};
+
+static int class_of(const za_problem& p) { return (p.dim == 2 ? 2 : 0) + (p.precision == ZA_FP32_RECON ? 1 : 0); }
+static int ncomp(const za_problem& p) { return p.dim == 1 ? 3 : 4; }
+
+struct GraphKey {
+  int xcap, ycap, ncap;
+  bool operator<(const GraphKey& o) const {
+    return xcap != o.xcap ? xcap < o.xcap : (ycap != o.ycap ? ycap < o.ycap : ncap < o.ncap);
+  }
+};
+
+struct Class {
+  hipStream_t stream = nullptr;
+  BatchTable* dtab = nullptr;
+  BatchTable* htab = nullptr;     // pinned mirror
+  DevCtl* dctl = nullptr;         // MAX_SLOTS control blocks
+  DevCtl* hctl = nullptr;         // pinned mirror
+  std::vector<Req*> active;
+  std::vector<int> free_slots;
+  bool dirty = false;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+}  // namespace zs
+
+using namespace zs;
+
+struct za_server {
+  size_t budget = 0;
+  int max_slots = 0;
+  int device = 0;
+  char* pool_base = nullptr;
+  Pool pool;
+  Class cls[NCLASS];
+  std::deque<Req*> waiting;
+  std::map<za_req_id, std::unique_ptr<Req>> reqs;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::thread th;
+  bool stop = false;
+  za_req_id next_id = 1;
+  int64_t in_flight = 0;   // submitted and not finished
+  std::string err;
+};
+
+static size_t footprint(const za_problem& p, int* stage_blocks, int* xblocks, int* ystrips, int* yblocks) {
+  const int m = ncomp(p);
+  const size_t S = (size_t)m * p.nx * p.ny * sizeof(double);
+  const long long nseg = (p.nx + XS_CELLS - 1) / XS_CELLS;
+  *xblocks = (int)((nseg * p.ny + 3) / 4);
+  if (p.dim == 2) {
+    *ystrips = (p.nx + 63) / 64;
+    *yblocks = *ystrips * ((p.ny + SERVE_YTILE - 1) / SERVE_YTILE);
+    *stage_blocks = *yblocks;
+  } else {
+    *ystrips = 0;
+    *yblocks = 0;
+    *stage_blocks = *xblocks;
+  }
+  const size_t part = ((size_t)*stage_blocks * NPART * sizeof(double) + 255) & ~size_t(255);
+  return (p.dim == 2 ? 4 : 3) * ((S + 255) & ~size_t(255)) + part;
+}
+
+static int pow2_cap(int n, int lo) {
+  int c = lo;
+  while (c < n) c <<= 1;
+  return c;
+}
+
+// Launch one RK3 step of a class (captured into a graph per capacity).
+static hipError_t class_step(za_server* sv, int c) {
+  Class& C = sv->cls[c];
+  const BatchTable& h = *C.htab;
+  const bool two_d = c >= 2, fp32 = (c & 1) != 0;
+  GraphKey key{pow2_cap(h.xtot, 64), two_d ? pow2_cap(h.ytot, 64) : 0, pow2_cap(h.n, 8)};
+  auto it = C.graphs.find(key);
+  if (it == C.graphs.end()) {
+    hipGraph_t g;
+    hipError_t e = hipStreamBeginCapture(C.stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    for (int s = 0; s < 3; ++s) {
+      hipLaunchKernelGGL(kb_final, dim3(key.ncap), dim3(64), 0, C.stream, C.dtab, s == 0 ? FIN_STAGE0 : FIN_STAGEK,
+                         two_d ? 2 : 1);
+      if (two_d) {
+        if (fp32) {
+          hipLaunchKernelGGL((kb_sweep_x<4, float>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
+          hipLaunchKernelGGL((kb_sweep_y<float>), dim3(key.ycap), dim3(256), 0, C.stream, C.dtab, s);
+        } else {
+          hipLaunchKernelGGL((kb_sweep_x<4, double>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
+          hipLaunchKernelGGL((kb_sweep_y<double>), dim3(key.ycap), dim3(256), 0, C.stream, C.dtab, s);
+        }
+      } else {
+        if (fp32)
+          hipLaunchKernelGGL((kb_sweep_x<3, float>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
+        else
+          hipLaunchKernelGGL((kb_sweep_x<3, double>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
+      }
+    }
+    hipLaunchKernelGGL(kb_step_end, dim3(key.ncap), dim3(64), 0, C.stream, C.dtab);
+    e = hipStreamEndCapture(C.stream, &g);
+    if (e != hipSuccess) return e;
+    hipGraphExec_t ex;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    it = C.graphs.emplace(key, ex).first;
+  }
+  return hipGraphLaunch(it->second, C.stream);
+}
+
+static void rebuild_table(Class& C) {
+  BatchTable& h = *C.htab;
+  h.n = (int)C.active.size();
+  int x = 0, y = 0;
+  for (int i = 0; i < h.n; ++i) {
+    h.s[i] = C.active[i]->desc;
+    h.xoff[i] = x;
+    h.yoff[i] = y;
+    x += h.s[i].xblocks;
+    y += h.s[i].yblocks;
+  }
+  h.xoff[h.n] = x;
+  h.yoff[h.n] = y;
+  h.xtot = x;
+  h.ytot = y;
+}
+
+// Admit waiting requests that fit (first fit in arrival order).  Called with
+// the lock held; the uploads run on the class streams.
+static void admit(za_server* sv) {
+  int total = 0;
+  for (int c = 0; c < NCLASS; ++c) total += (int)sv->cls[c].active.size();
+  for (auto it = sv->waiting.begin(); it != sv->waiting.end();) {
+    Req* r = *it;
+    Class& C = sv->cls[r->cls];
+    if (total >= sv->max_slots) break;
+    if (C.free_slots.empty()) { ++it; continue; }
+    int sb, xb, ys, yb;
+    const size_t need = footprint(r->prob, &sb, &xb, &ys, &yb);
+    size_t off;
+    if (!sv->pool.alloc(need, &off)) { ++it; continue; }
+    r->off = off;
+    r->bytes = need;
+    r->slot = C.free_slots.back();
+    C.free_slots.pop_back();
+    const size_t S = ((r->m * r->ncell * sizeof(double)) + 255) & ~size_t(255);
+    char* base = sv->pool_base + off;
+    SlotDesc& d = r->desc;
+    std::memset(&d, 0, sizeof(d));
+    d.st = (double*)base;
+    d.q1 = (double*)(base + S);
+    d.q2 = (double*)(base + 2 * S);
+    d.lx = r->prob.dim == 2 ? (double*)(base + 3 * S) : nullptr;
+    d.part = (double*)(base + (r->prob.dim == 2 ? 4 : 3) * S);
+    d.ctl = C.dctl + r->slot;
+    const za_problem& p = r->prob;
+    d.g.nx = p.nx; d.g.ny = p.ny; d.g.bc_x = p.bc_x; d.g.bc_y = p.bc_y;
+    d.g.dx = (p.xhi - p.xlo) / p.nx;
+    d.g.dy = p.dim == 2 ? (p.yhi - p.ylo) / p.ny : 1.0;
+    d.g.inv_dx = 1.0 / d.g.dx;
+    d.g.inv_dy = 1.0 / d.g.dy;
+    d.ph.gamma = p.gamma; d.ph.gm1 = p.gamma - 1.0;
+    d.ph.adv[0] = p.adv_speed[0]; d.ph.adv[1] = p.adv_speed[1];
+    d.ph.cfl = p.cfl; d.ph.dt_rule = p.dt_rule; d.ph.lf_scalar = p.lf == ZA_LF_SCALAR ? 1 : 0;
+    d.eps16 = 16.0 * p.eps; d.eps4 = 4.0 * p.eps; d.mu0x2 = 2.0 * p.mu0;
+    d.xblocks = xb; d.ystrips = ys; d.yblocks = yb; d.stage_blocks = sb;
+    // upload, control block, and the wave speeds of Q^0
+    (void)hipMemcpyAsync(d.st, r->q0.data(), r->m * r->ncell * sizeof(double), hipMemcpyHostToDevice, C.stream);
+    DevCtl v;
+    std::memset(&v, 0, sizeof(v));
+    v.t_final = std::numeric_limits<double>::infinity();
+    v.dt_min = std::numeric_limits<double>::infinity();
+    v.bad_step = -1;
+    v.active = 1;
+    v.max_steps = r->n_steps;
+    hipLaunchKernelGGL(k_ctl_set, dim3(1), dim3(64), 0, C.stream, d.ctl, v);
+    if (p.dim == 2)
+      hipLaunchKernelGGL((k_wave_partial<SYS_EULER, 4>), dim3(sb), dim3(256), 0, C.stream, d.st, r->ncell, d.ph,
+                         d.ctl, 0, d.part);
+    else
+      hipLaunchKernelGGL((k_wave_partial<SYS_EULER, 3>), dim3(sb), dim3(256), 0, C.stream, d.st, r->ncell, d.ph,
+                         d.ctl, 0, d.part);
+    (void)hipStreamSynchronize(C.stream);   // q0 may be released after this
+    std::vector<double>().swap(r->q0);
+    r->admitted = true;
+    r->t_adm = now_ns();
+    C.active.push_back(r);
+    C.dirty = true;
+    ++total;
+    it = sv->waiting.erase(it);
+  }
+}
+
+static void scheduler(za_server* sv) {
+  (void)hipSetDevice(sv->device);
+  std::unique_lock<std::mutex> lk(sv->mu);
+  while (true) {
+    admit(sv);
+    bool any = false;
+    for (int c = 0; c < NCLASS; ++c) any = any || !sv->cls[c].active.empty();
+    if (!any) {
+      if (sv->stop) break;
+      sv->cv_work.wait(lk, [&] { return sv->stop || !sv->waiting.empty(); });
+      continue;
+    }
+    // table uploads and one RK3 step per class (streams overlap)
+    for (int c = 0; c < NCLASS; ++c) {
+      Class& C = sv->cls[c];
+      if (C.active.empty()) continue;
+      if (C.dirty) {
+        rebuild_table(C);
+        (void)hipMemcpyAsync(C.dtab, C.htab, sizeof(BatchTable), hipMemcpyHostToDevice, C.stream);
+        C.dirty = false;
+      }
+      if (class_step(sv, c) != hipSuccess) sv->err = "graph launch failed";
+      (void)hipMemcpyAsync(C.hctl, C.dctl, MAX_SLOTS * sizeof(DevCtl), hipMemcpyDeviceToHost, C.stream);
+    }
+    lk.unlock();
+    for (int c = 0; c < NCLASS; ++c)
+      if (!sv->cls[c].active.empty()) (void)hipStreamSynchronize(sv->cls[c].stream);
+    lk.lock();
+    // retire finished requests
+    for (int c = 0; c < NCLASS; ++c) {
+      Class& C = sv->cls[c];
+      for (size_t i = 0; i < C.active.size();) {
+        Req* r = C.active[i];
+        const DevCtl& h = C.hctl[r->slot];
+        if (h.active) { ++i; continue; }
+        r->steps = h.steps;
+        const long long irs = r->prob.dim == 2 ? (long long)(r->prob.nx + 1) * r->prob.ny +
+                                                     (long long)r->prob.nx * (r->prob.ny + 1)
+                                               : (long long)(r->prob.nx + 1);
+        r->interfaces = 3 * irs * h.steps;
+        r->status = h.bad ? ZA_ERR_NONFINITE : ZA_OK;
+        r->qout.resize(r->m * r->ncell);
+        (void)hipMemcpy(r->qout.data(), r->desc.st, r->m * r->ncell * sizeof(double), hipMemcpyDeviceToHost);
+        sv->pool.release(r->off, r->bytes);
+        C.free_slots.push_back(r->slot);
+        r->slot = -1;
+        r->done = true;
+        r->t_fin = now_ns();
+        sv->in_flight--;
+        C.active.erase(C.active.begin() + i);
+        C.dirty = true;
+      }
+    }
+    sv->cv_done.notify_all();
+  }
+}
 
 extern "C" {
-za_status za_server_create(size_t, int32_t, int32_t, za_server** out) {
-  if (out) *out = nullptr;
-  return ZA_ERR_UNSUPPORTED;
+
+za_status za_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t device, za_server** out) {
+  if (!out) return ZA_ERR_ARG;
+  *out = nullptr;
+  if (hbm_budget_bytes < (1u << 20) || max_slots < 1 || max_slots > MAX_SLOTS) return ZA_ERR_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return ZA_ERR_ARG;
+  auto sv = std::make_unique<za_server>();
+  sv->budget = hbm_budget_bytes;
+  sv->max_slots = max_slots;
+  sv->device = device;
+  if (hipSetDevice(device) != hipSuccess) return ZA_ERR_DEVICE;
+  void* p = nullptr;
+  if (hipMalloc(&p, hbm_budget_bytes) != hipSuccess) return ZA_ERR_NOMEM;
+  sv->pool_base = (char*)p;
+  sv->pool.init(hbm_budget_bytes);
+  for (int c = 0; c < NCLASS; ++c) {
+    Class& C = sv->cls[c];
+    if (hipStreamCreate(&C.stream) != hipSuccess) return ZA_ERR_DEVICE;
+    if (hipMalloc(&p, sizeof(BatchTable)) != hipSuccess) return ZA_ERR_NOMEM;
+    C.dtab = (BatchTable*)p;
+    if (hipHostMalloc(&p, sizeof(BatchTable), hipHostMallocDefault) != hipSuccess) return ZA_ERR_NOMEM;
+    C.htab = (BatchTable*)p;
+    std::memset(C.htab, 0, sizeof(BatchTable));
+    if (hipMalloc(&p, MAX_SLOTS * sizeof(DevCtl)) != hipSuccess) return ZA_ERR_NOMEM;
+    C.dctl = (DevCtl*)p;
+    if (hipHostMalloc(&p, MAX_SLOTS * sizeof(DevCtl), hipHostMallocDefault) != hipSuccess) return ZA_ERR_NOMEM;
+    C.hctl = (DevCtl*)p;
+    std::memset(C.hctl, 0, MAX_SLOTS * sizeof(DevCtl));
+    for (int s = MAX_SLOTS - 1; s >= 0; --s) C.free_slots.push_back(s);
+    (void)hipMemcpy(C.dtab, C.htab, sizeof(BatchTable), hipMemcpyHostToDevice);
+  }
+  za_server* raw = sv.release();
+  raw->th = std::thread(scheduler, raw);
+  *out = raw;
+  return ZA_OK;
 }
-za_status za_server_submit(za_server*, const za_problem*, const double*, int64_t, za_req_id*) {
-  return ZA_ERR_UNSUPPORTED;
+
+za_status za_server_submit(za_server* sv, const za_problem* p, const double* q0, int64_t n_steps, za_req_id* id) {
+  if (!sv || !p || !q0 || !id || n_steps < 1) return ZA_ERR_ARG;
+  std::string why;
+  if (za_validate(p, &why) != ZA_OK) return ZA_ERR_ARG;
+  // batches run the paper's weights (Z type, p = 1, mu = 1) on the Euler equations
+  if (p->system != ZA_EULER || p->p != 1.0 || p->affine_invariant || p->linear_weights) return ZA_ERR_UNSUPPORTED;
+  int sb, xb, ys, yb;
+  if (footprint(*p, &sb, &xb, &ys, &yb) > sv->budget) return ZA_ERR_NOMEM;
+  auto r = std::make_unique<Req>();
+  r->prob = *p;
+  r->cls = class_of(*p);
+  r->m = ncomp(*p);
+  r->ncell = (size_t)p->nx * p->ny;
+  r->q0.assign(q0, q0 + r->m * r->ncell);
+  r->n_steps = n_steps;
+  r->t_arr = now_ns();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) return ZA_ERR_ARG;
+    r->id = sv->next_id++;
+    *id = r->id;
+    sv->waiting.push_back(r.get());
+    sv->reqs.emplace(r->id, std::move(r));
+    sv->in_flight++;
+  }
+  sv->cv_work.notify_one();
+  return ZA_OK;
 }
-za_status za_server_poll(za_server*, za_req_id, int32_t*, double*, za_req_stats*) { return ZA_ERR_UNSUPPORTED; }
-za_status za_server_drain(za_server*) { return ZA_ERR_UNSUPPORTED; }
-za_status za_server_destroy(za_server*) { return ZA_ERR_UNSUPPORTED; }
+
+za_status za_server_poll(za_server* sv, za_req_id id, int32_t* done, double* q_out, za_req_stats* st) {
+  if (!sv || !done) return ZA_ERR_ARG;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(id);
+  if (it == sv->reqs.end()) return ZA_ERR_ARG;
+  Req* r = it->second.get();
+  *done = r->done ? 1 : 0;
+  if (st) {
+    st->arrival_ns = r->t_arr;
+    st->admit_ns = r->t_adm;
+    st->finish_ns = r->t_fin;
+    st->steps = r->steps;
+    st->interfaces = r->interfaces;
+    st->status = r->status;
+  }
+  if (r->done && q_out) {
+    std::memcpy(q_out, r->qout.data(), r->qout.size() * sizeof(double));
+    const za_status s = (za_status)r->status;
+    sv->reqs.erase(it);
+    return s;
+  }
+  return r->done ? (za_status)r->status : ZA_OK;
 }
+
+za_status za_server_drain(za_server* sv) {
+  if (!sv) return ZA_ERR_ARG;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  sv->cv_done.wait(lk, [&] { return sv->in_flight == 0; });
+  return sv->err.empty() ? ZA_OK : ZA_ERR_DEVICE;
+}
+
+za_status za_server_destroy(za_server* sv) {
+  if (!sv) return ZA_ERR_ARG;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+    sv->waiting.clear();
+  }
+  sv->cv_work.notify_all();
+  if (sv->th.joinable()) sv->th.join();
+  for (int c = 0; c < NCLASS; ++c) {
+    Class& C = sv->cls[c];
+    if (C.stream) (void)hipStreamSynchronize(C.stream);
+    for (auto& kv : C.graphs) (void)hipGraphExecDestroy(kv.second);
+    if (C.dtab) (void)hipFree(C.dtab);
+    if (C.htab) (void)hipHostFree(C.htab);
+    if (C.dctl) (void)hipFree(C.dctl);
+    if (C.hctl) (void)hipHostFree(C.hctl);
+    if (C.stream) (void)hipStreamDestroy(C.stream);
+  }
+  if (sv->pool_base) (void)hipFree(sv->pool_base);
+  delete sv;
+  return ZA_OK;
+}
+
+}  // extern "C"

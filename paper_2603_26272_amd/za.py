@@ -237,3 +237,68 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Server:
+    """Continuous-batching solve server (za_server_*): requests are admitted
+    by HBM footprint and advanced together by batched RK3 steps."""
+
+    def __init__(self, hbm_budget_bytes: int = 4 << 30, max_slots: int = 64, device: int = 0):
+        h = C.c_void_p()
+        st = lib().za_server_create(C.c_size_t(int(hbm_budget_bytes)), int(max_slots), int(device), C.byref(h))
+        if st != ZA_OK:
+            raise ZaError(st, status_str(st))
+        self._h = h
+
+    def submit(self, P: Problem, q0, n_steps: int) -> int:
+        import numpy as np
+        q = np.ascontiguousarray(q0, dtype=np.float64)
+        if q.shape != tuple(P.shape):
+            raise ValueError(f"q0 has shape {q.shape}, expected {tuple(P.shape)}")
+        z = ZaProblem.from_problem(P)
+        rid = C.c_int64(0)
+        st = lib().za_server_submit(self._h, C.byref(z), q.ctypes.data_as(C.POINTER(C.c_double)), int(n_steps),
+                                    C.byref(rid))
+        if st != ZA_OK:
+            raise ZaError(st, status_str(st))
+        return rid.value
+
+    def poll(self, rid: int, P: Optional[Problem] = None):
+        """(done, status, q or None, stats).  With P given and the request
+        finished, the result is returned and the request released."""
+        import numpy as np
+        done = C.c_int32(0)
+        stats = ZaReqStats()
+        out = np.empty(P.shape, dtype=np.float64) if P is not None else None
+        st = lib().za_server_poll(self._h, int(rid), C.byref(done),
+                                  out.ctypes.data_as(C.POINTER(C.c_double)) if out is not None else None,
+                                  C.byref(stats))
+        if st == ZA_ERR_ARG:
+            raise ZaError(st, "unknown request")
+        s = {"arrival_ns": stats.arrival_ns, "admit_ns": stats.admit_ns, "finish_ns": stats.finish_ns,
+             "steps": stats.steps, "interfaces": stats.interfaces, "status": stats.status}
+        if not done.value:
+            return False, ZA_OK, None, s
+        return True, stats.status, out, s
+
+    def drain(self):
+        st = lib().za_server_drain(self._h)
+        if st != ZA_OK:
+            raise ZaError(st, status_str(st))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().za_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
