@@ -33,6 +33,7 @@ FLOPS_2D = {
     "x": {"interface": 1371.0, "cell_flux": 15.0, "cell_update": 8},
     "y": {"interface": 1371.0, "cell_flux": 15.0, "cell_update": 32},
 }
+FLOPS_1D_IR = 1000.0 + 10.0   # 1D Euler: per interface + per-cell physical flux
 PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (packed issue)
 PEAK_HBM_GBS = 8000.0
@@ -99,6 +100,53 @@ def cpu_baseline(P, q0_np, seconds):
                       f"OpenMP over rows"}
 
 
+def run_serving(lam, n_requests, budget, slots, seed=None, max_1d=65536, max_2d=1024):
+    """Replay a seeded Poisson stream against the continuous-batching server.
+    Latency is measured from each request's scheduled arrival time to the
+    server's finish timestamp (host steady clock)."""
+    import numpy as np
+
+    from paper_2603_26272_amd import workloads as W
+    from paper_2603_26272_amd.za import Server
+
+    reqs = W.serving_stream(lam, n_requests=n_requests, seed=seed, max_1d=max_1d, max_2d=max_2d)
+    ids = [None] * len(reqs)
+    with Server(budget, slots) as sv:
+        t0 = time.perf_counter()
+        t0_ns = time.monotonic_ns()
+        for i, r in enumerate(reqs):
+            dt = t0 + r.arrival - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            ids[i] = sv.submit(r.problem, r.q0, r.steps)
+        sv.drain()
+        t1 = time.perf_counter()
+        lat, irs, fl, statuses, waits = [], 0, 0.0, [], []
+        first_arr = None
+        last_fin = 0
+        for r, rid in zip(reqs, ids):
+            done, st, q, stats = sv.poll(rid, r.problem)
+            statuses.append(st)
+            # the server stamps with the same monotonic clock as time.monotonic_ns
+            arr = t0_ns + int(r.arrival * 1e9)      # scheduled arrival
+            lat.append((stats["finish_ns"] - arr) * 1e-9)
+            waits.append((stats["admit_ns"] - stats["arrival_ns"]) * 1e-9)
+            irs += stats["interfaces"]
+            m = r.problem.m
+            per_ir = FLOPS_2D["x"]["interface"] if m == 4 else FLOPS_1D_IR
+            fl += stats["interfaces"] * per_ir
+            first_arr = arr if first_arr is None else min(first_arr, arr)
+            last_fin = max(last_fin, stats["finish_ns"])
+    span = (last_fin - first_arr) * 1e-9
+    lat = np.array(lat)
+    return {"rate_req_s": lam, "requests": n_requests, "ok": int(sum(1 for s in statuses if s == 0)),
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_admission_wait_s": float(np.mean(waits)),
+            "throughput_req_s": n_requests / span, "throughput_IR_s": irs / span,
+            "roofline_frac": fl / span / (PEAK_FP64_TFLOPS * 1e12), "makespan_s": span,
+            "wall_s": t1 - t0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +157,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-rates", type=str, default="50,200",
+                    help="Poisson rates (req/s) of the serving leg; the full sweep is 10,25,50,100,200")
+    ap.add_argument("--serving-requests", type=int, default=128)
+    ap.add_argument("--serving-budget-gb", type=float, default=4.0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -179,6 +232,17 @@ def main():
                        "density_err_vs_fp64": {"l1": float(e.mean()), "linf": float(e.max())},
                        "avg_launch_ms": {names[k]: avg32[k] for k in range(3)},
                        "speedup_vs_fp64": wall / wall32}
+
+    if not args.no_serving:
+        rates = [float(x) for x in args.serving_rates.split(",") if x]
+        runs = [run_serving(lam, args.serving_requests, int(args.serving_budget_gb * (1 << 30)), 64)
+                for lam in rates]
+        out["serving"] = {"workload": "Poisson stream: half 1D Euler N log-uniform [512, 65536], half 2D "
+                                      "Euler n x n log-uniform [128, 1024]; Riemann or smooth data; 50-500 "
+                                      "RK3 steps; FP64 or FP32 reconstruction (seed = rate)",
+                          "hbm_budget_gb": args.serving_budget_gb, "max_slots": 64, "runs": runs}
+        out["p50_latency_s"] = runs[-1]["p50_latency_s"]
+        out["p99_latency_s"] = runs[-1]["p99_latency_s"]
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(P, q0, args.cpu_seconds)
