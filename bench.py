@@ -147,6 +147,132 @@ def run_serving(lam, n_requests, budget, slots, seed=None, max_1d=65536, max_2d=
             "wall_s": t1 - t0}
 
 
+# ---------------------------------------------------------------------------
+# studies of the other workloads (python bench.py --study NAME); each prints
+# one JSON line of its own
+# ---------------------------------------------------------------------------
+def study_c0(torch, Context):
+    """Smooth advection u_t + u_x = 0, sin(pi x), periodic [-1,1], T = 2,
+    dt = 0.5 dx^2: GPU errors, observed orders, GPU and oracle time."""
+    import math
+
+    import numpy as np
+
+    import oracle
+    from paper_2603_26272_amd import workloads as W
+    rows = []
+    for N in (25, 50, 100, 200, 400):
+        P, q0 = W.advection_sine(N)
+        q = torch.from_numpy(q0).to("cuda")
+        with Context(P) as ctx:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = ctx.solve(q, 2.0)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        x = W.centres(N, -1.0, 1.0)
+        e = np.abs(q.cpu().numpy()[0, 0] - np.sin(math.pi * (x - 2.0)))
+        row = {"N": N, "steps": info["steps"], "linf": float(e.max()), "l1": float(e.mean()),
+               "gpu_s": t1 - t0, "gpu_IR_s": 3 * (N + 1) * info["steps"] / (t1 - t0)}
+        if N <= 200:
+            t0 = time.perf_counter()
+            qo, *_ = oracle.solve(P, q0, 2.0)
+            row["oracle_s"] = time.perf_counter() - t0
+            row["max_abs_diff_vs_oracle"] = float(np.abs(qo - q.cpu().numpy()).max())
+        rows.append(row)
+    for a, b in zip(rows, rows[1:]):
+        b["order_linf"] = math.log2(a["linf"] / b["linf"])
+        b["order_l1"] = math.log2(a["l1"] / b["l1"])
+    return {"study": "c0 smooth advection convergence (FP64)", "rows": rows,
+            "oracle_threads": oracle.get_threads()}
+
+
+def study_c1(torch, Context, seeds=16, steps=2000):
+    """1D Euler N = 4096, 2000 CFL steps: one request alone (GPU context, graph
+    replay), all seeds batched through the server, and the oracle on seed 0."""
+    import numpy as np
+
+    import oracle
+    from paper_2603_26272_amd import workloads as W
+    from paper_2603_26272_amd.za import Server
+    P, q0 = W.riemann_1d(0, 4096)
+    ir_run = 3 * 4097 * steps
+    q = torch.from_numpy(q0).to("cuda")
+    with Context(P) as ctx:
+        ctx.solve(q.clone(), 0.0, 20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = ctx.solve(q, 0.0, steps)
+        torch.cuda.synchronize()
+        t_alone = time.perf_counter() - t0
+    gpu0 = q.cpu().numpy()
+    probs = [W.riemann_1d(s, 4096) for s in range(seeds)]
+    with Server(1 << 30, 64) as sv:
+        t0 = time.perf_counter()
+        ids = [sv.submit(Pk, qk, steps) for Pk, qk in probs]
+        sv.drain()
+        t_batch = time.perf_counter() - t0
+        served0 = sv.poll(ids[0], probs[0][0])[2]
+    t0 = time.perf_counter()
+    ref, *_ = oracle.solve(P, q0, 0.0, steps)
+    t_orc = time.perf_counter() - t0
+    scale = np.abs(ref).max(axis=(1, 2), keepdims=True)
+    return {"study": "c1 1D Euler N=4096, 2000 steps (FP64)",
+            "alone": {"s": t_alone, "IR_s": ir_run / t_alone, "t_final": info["t"]},
+            "batched": {"seeds": seeds, "s": t_batch, "IR_s": seeds * ir_run / t_batch},
+            "oracle": {"s": t_orc, "IR_s": ir_run / t_orc, "threads": 1},
+            "seed0_max_rel_diff_vs_oracle": float((np.abs(gpu0 - ref) / (np.abs(ref) + scale)).max()),
+            "served_equals_alone_bitwise": bool(np.array_equal(served0, gpu0))}
+
+
+def study_c3(torch, Context, n=4096, steps=200):
+    """Precision: 2D quadrants at 4096^2 in FP64 and FP32 reconstruction, and
+    the smooth 2D density wave at 128^2 .. 1024^2 (T = 0.05, dt = 0.5 h^2)."""
+    import math
+
+    import numpy as np
+
+    from paper_2603_26272_amd import workloads as W
+    out = {"study": "c3 FP32 reconstruction vs FP64"}
+    P, q0 = W.quadrants_2d(0, n)
+    res = {}
+    for name, PP in (("fp64", P), ("fp32", P.fp32())):
+        q = torch.from_numpy(q0).to("cuda")
+        with Context(PP) as ctx:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.solve(q, 0.0, steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        res[name] = (q[0].clone(), dt)
+        del q
+    e = (res["fp32"][0] - res["fp64"][0]).abs()
+    ir = 3 * ir_per_rhs(n, n) * steps
+    out["quadrants_4096"] = {"steps": steps, "fp64_IR_s": ir / res["fp64"][1], "fp32_IR_s": ir / res["fp32"][1],
+                             "density_l1": float(e.mean()), "density_linf": float(e.max())}
+    rows = []
+    for m in (128, 256, 512, 1024):
+        row = {"n": m}
+        Pw, qw = W.smooth_wave_2d(m)
+        exact = W.smooth_wave_2d_exact(m, 0.05)
+        for name, PP in (("fp64", Pw), ("fp32", Pw.fp32())):
+            q = torch.from_numpy(qw).to("cuda")
+            with Context(PP) as ctx:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = ctx.solve(q, 0.05)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            err = np.abs(q[0].cpu().numpy() - exact)
+            row[name] = {"linf": float(err.max()), "l1": float(err.mean()), "steps": info["steps"], "s": dt}
+        rows.append(row)
+    for a, b in zip(rows, rows[1:]):
+        for name in ("fp64", "fp32"):
+            b[name]["order_l1"] = math.log2(a[name]["l1"] / b[name]["l1"])
+    out["smooth_wave"] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +288,8 @@ def main():
                     help="Poisson rates (req/s) of the serving leg; the full sweep is 10,25,50,100,200")
     ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--serving-budget-gb", type=float, default=4.0)
+    ap.add_argument("--study", choices=["c0", "c1", "c3", "serving"], default=None,
+                    help="run one workload study instead of the benchmark line")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -176,6 +304,20 @@ def main():
     from paper_2603_26272_amd.za import Context
 
     torch.cuda.set_device(0)
+    if args.study:
+        if args.study == "c0":
+            res = study_c0(torch, Context)
+        elif args.study == "c1":
+            res = study_c1(torch, Context)
+        elif args.study == "c3":
+            res = study_c3(torch, Context)
+        else:
+            rates = [float(x) for x in args.serving_rates.split(",") if x]
+            res = {"study": "serving sweep", "hbm_budget_gb": args.serving_budget_gb,
+                   "runs": [run_serving(lam, args.serving_requests, int(args.serving_budget_gb * (1 << 30)), 64)
+                            for lam in rates]}
+        print(json.dumps(res), flush=True)
+        return
     P, q0 = W.quadrants_2d(args.seed, args.n)
     nx, ny = P.nx, P.ny
     ir_step = 3 * ir_per_rhs(nx, ny)

@@ -26,6 +26,10 @@ struct za_ctx {
   int stage_blocks = 1;      // blocks of the kernel that writes a stage state
   int part_blocks = 1;       // capacity of `part` in blocks
   bool speeds_valid = false; // part holds the wave speeds of the current q
+  bool graphs_ok = true;     // step graphs usable on this device
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;  // GRAPH_STEPS steps for state graph_q
+  const double* graph_q = nullptr;
   int chunk_steps = 0;       // steps per host check in za_solve (0: default)
   bool timing = false;
   hipEvent_t ev_open[3] = {nullptr, nullptr, nullptr};

@@ -335,6 +335,54 @@ static za_status enqueue_step(za_ctx* c, double* q) {
   return ZA_OK;
 }
 
+// n RK3 steps.  After the first step of an API call (which may need the
+// stand-alone wave-speed pass), runs of GRAPH_STEPS steps replay a hipGraph
+// captured once per state pointer on a private capture stream; kernels read
+// dt and the LF speeds from the device control block, so a graph is valid
+// for any step.  Kernel timing (events) uses direct launches.
+static constexpr int GRAPH_STEPS = 16;
+
+static za_status enqueue_steps(za_ctx* c, double* q, int64_t n) {
+  za_status st;
+  int64_t done = 0;
+  if (n > 0 && !c->speeds_valid) {
+    if ((st = enqueue_step(c, q)) != ZA_OK) return st;
+    done = 1;
+  }
+  if (!c->timing && c->graphs_ok && n - done >= GRAPH_STEPS) {
+    if (!c->graph_exec || c->graph_q != q) {
+      if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+      if (!c->capture_stream && hipStreamCreate(&c->capture_stream) != hipSuccess) c->graphs_ok = false;
+      if (c->graphs_ok) {
+        hipStream_t user = c->stream;
+        c->stream = c->capture_stream;
+        hipGraph_t g = nullptr;
+        bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        for (int i = 0; ok && i < GRAPH_STEPS; ++i) ok = enqueue_step(c, q) == ZA_OK;
+        ok = (hipStreamEndCapture(c->stream, &g) == hipSuccess) && ok;
+        c->stream = user;
+        if (ok) ok = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+        if (!ok) {
+          c->graphs_ok = false;
+          c->graph_exec = nullptr;
+          (void)hipGetLastError();
+        } else {
+          c->graph_q = q;
+        }
+      }
+    }
+    while (c->graph_exec && n - done >= GRAPH_STEPS) {
+      hipError_t e = hipGraphLaunch(c->graph_exec, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+      done += GRAPH_STEPS;
+    }
+  }
+  for (; done < n; ++done)
+    if ((st = enqueue_step(c, q)) != ZA_OK) return st;
+  return ZA_OK;
+}
+
 static DevCtl fresh_ctl() {
   DevCtl v;
   std::memset(&v, 0, sizeof(v));
@@ -418,6 +466,8 @@ za_status za_ctx_destroy(za_ctx* c) {
   for (int k = 0; k < 3; ++k) {
     for (auto& pr : c->events[k]) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
   }
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   if (c->q1) hipFree(c->q1);
   if (c->q2) hipFree(c->q2);
   if (c->lx) hipFree(c->lx);
@@ -511,9 +561,11 @@ za_status za_solve(za_ctx* c, double* q, double t_final, int64_t max_steps, za_s
     const int64_t n_equal = std::min<int64_t>(n_run, n - 1);
     hipLaunchKernelGGL(k_ctl_arm, dim3(1), dim3(64), 0, c->stream, c->ctl, dt,
                        std::numeric_limits<double>::infinity(), (long long)n_equal);
-    for (int64_t s = 0; s < n_equal; ++s) {
-      if ((st = enqueue_step(c, q)) != ZA_OK) return st;
-      if ((s + 1) % (64 * chunk) == 0) {
+    for (int64_t s = 0; s < n_equal;) {
+      const int64_t k = std::min<int64_t>(n_equal - s, 64 * (int64_t)chunk);
+      if ((st = enqueue_steps(c, q, k)) != ZA_OK) return st;
+      s += k;
+      if (s < n_equal) {
         if ((st = read_ctl(c, &h)) != ZA_OK) return st;
         if (h.bad) break;
       }
@@ -536,8 +588,7 @@ za_status za_solve(za_ctx* c, double* q, double t_final, int64_t max_steps, za_s
     while (true) {
       int n = chunk;
       if (t_final <= 0.0) n = (int)std::min<int64_t>(chunk, max_steps - enqueued);
-      for (int s = 0; s < n; ++s)
-        if ((st = enqueue_step(c, q)) != ZA_OK) return st;
+      if ((st = enqueue_steps(c, q, n)) != ZA_OK) return st;
       enqueued += n;
       if ((st = read_ctl(c, &h)) != ZA_OK) return st;
       if (!h.active || h.bad) break;
