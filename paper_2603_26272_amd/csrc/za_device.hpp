@@ -51,6 +51,23 @@ __device__ __forceinline__ double div_nr(double a, double x) {
   return fma(fma(-x, q, a), r, q);
 }
 __device__ __forceinline__ float rcp_nr(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Square root of a positive normal number from the hardware reciprocal square
+// root estimate: one Goldschmidt iteration (s -> sqrt(x), h -> 1/(2 sqrt(x)))
+// followed by two residual corrections s <- s + h (x - s^2), which round
+// correctly for estimates within 1e-7.  Densities and squared sound speeds
+// stay far from the denormal and overflow ranges, so the exponent scaling of
+// the library square root is not needed.
+__device__ __forceinline__ double sqrt_nr(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  double s = x * r, h = 0.5 * r;
+  const double e = fma(-h, s, 0.5);
+  s = fma(s, e, s);
+  h = fma(h, e, h);
+  s = fma(fma(-s, s, x), h, s);
+  return fma(fma(-s, s, x), h, s);
+}
+__device__ __forceinline__ float sqrt_nr(float x) { return sqrtf(x); }
 __device__ __forceinline__ float div_nr(float a, float x) { return a * __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------------------
@@ -93,16 +110,18 @@ __device__ __forceinline__ float div_nr(float a, float x) { return a * __builtin
 // ---------------------------------------------------------------------------
 template <class T, int WV>
 __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const WeightCfg<T>& w) {
-  const T c13 = T(1) / T(3), c16 = T(1) / T(6), c56 = T(5) / T(6), c76 = T(7) / T(6),
-          c116 = T(11) / T(6);
-  const T q0 = fma(c116, s2, fma(-c76, s1, c13 * s0));
-  const T q1 = fma(c13, s3, fma(c56, s2, -c16 * s1));
-  const T q2 = fma(-c16, s4, fma(c56, s3, c13 * s2));
-  const T q3 = fma(c13, s5, fma(-c76, s4, c116 * s3));
+  const T c13 = T(1) / T(3), c16 = T(1) / T(6), c56 = T(5) / T(6);
+  // first and second differences; the candidates are written around the
+  // centre values: q_0 = s2 + (5 d1 - 2 d0)/6, q_1 = s2 + (d1 + 2 d2)/6,
+  // q_2 = s3 - (2 d2 + d3)/6, q_3 = s3 + (2 d4 - 5 d3)/6 (= <c_k, f_k>)
+  const T d0 = s1 - s0, d1 = s2 - s1, d2 = s3 - s2, d3 = s4 - s3, d4 = s5 - s4;
+  const T q0 = fma(c56, d1, fma(-c13, d0, s2));
+  const T q1 = fma(c13, d2, fma(c16, d1, s2));
+  const T q2 = fma(-c16, d3, fma(-c13, d2, s3));
+  const T q3 = fma(c13, d4, fma(-c56, d3, s3));
   if (WV == WV_GENERAL && w.linear) {
     return (q0 + q3 + T(9) * (q1 + q2)) * T(0.05);
   }
-  const T d0 = s1 - s0, d1 = s2 - s1, d2 = s3 - s2, d3 = s4 - s3, d4 = s5 - s4;
   const T e0 = d1 - d0, e1 = d2 - d1, e2 = d3 - d2, e3 = d4 - d3;
   const T g0 = fma(T(3), d1, -d0);       // s0 - 4 s1 + 3 s2
   const T g1 = d1 + d2;                  // -(s1 - s3)
@@ -207,7 +226,7 @@ __device__ __forceinline__ void euler_record(const double (&qd)[M], T gm1, T* re
     rec[Lo::Q2 * fs] = q2;
     rec[Lo::F2 * fs] = q2 * un;
   }
-  rec[Lo::SR * fs] = sqrt(q0);
+  rec[Lo::SR * fs] = sqrt_nr(q0);
 }
 
 // Velocities and total enthalpy of one record (the Roe ingredients).
@@ -263,7 +282,7 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
   const T H = fma(wl, Hl, wr * Hr);
   const T q2 = T(0.5) * fma(u, u, v * v);
   const T c2 = gm1 * (H - q2);
-  const T c = sqrt(c2);
+  const T c = sqrt_nr(c2);
   const T ic = rcp_nr(c);
   const T b1 = gm1 * (ic * ic);
   const T hb1 = T(0.5) * b1, hb2 = hb1 * q2;

@@ -106,7 +106,7 @@ __device__ __forceinline__ void cell_speeds(const double (&Q)[M], const Phys& ph
     const double c2 = ph.gamma * p * ir;
     const bool ok = rho > 0.0 && p > 0.0 && c2 > 0.0 && (E - E) == 0.0 && (mx - mx) == 0.0 && (my - my) == 0.0;
     if (!ok) { r[0] = __builtin_huge_val(); return; }
-    const double c = sqrt(c2);
+    const double c = sqrt_nr(c2);
     r[0] = wave_max(r[0], fabs(u - c));
     r[1] = wave_max(r[1], fabs(u));
     r[2] = wave_max(r[2], fabs(u + c));
@@ -123,14 +123,27 @@ __device__ __forceinline__ void cell_speeds(const double (&Q)[M], const Phys& ph
   }
 }
 
+// Index of the calling wavefront in its block, as a wave-uniform (scalar)
+// value so that everything derived from it stays in scalar registers.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// Orders LDS traffic among the lanes of one wavefront.  The LDS unit serves
+// a wavefront's requests in issue order, so it suffices to keep the compiler
+// from moving memory operations across this point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Block-wide maxima of r into dst[0..NPART); every thread of the block calls.
 __device__ __forceinline__ void block_max_store(double (&r)[NPART], double* __restrict__ dst) {
 #pragma unroll
   for (int i = 0; i < NPART; ++i) {
     for (int off = 32; off > 0; off >>= 1) r[i] = wave_max(r[i], __shfl_xor(r[i], off, 64));
   }
-  __shared__ double sm[4][NPART];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ double sm[8][NPART];
+  const int lane = threadIdx.x & 63, wv = wave_id();
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < NPART; ++i) sm[wv][i] = r[i];
@@ -264,7 +277,7 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
   constexpr int NF = NumFields<SYS, M>::value;
   __shared__ T xr[4][NF * XS_REC];
   __shared__ double fl[4][M][64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = wave_id();
   const int nx = a.g.nx, ny = a.g.ny;
   const int nseg = (nx + XS_CELLS - 1) / XS_CELLS;
   const long long wid = (long long)bid * 4 + wv;
@@ -280,7 +293,7 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
       stage_cell<SYS, M, 0, T>(a.q + row, cs, (size_t)j, a.ph, &xr[wv][idx], XS_REC);
     }
   }
-  __syncthreads();
+  wave_sync();   // the records and fluxes of a wavefront are its own
   if (live && k <= nx) {
     T F[M];
     const int off[6] = {lane, lane + 1, lane + 2, lane + 3, lane + 4, lane + 5};
@@ -296,7 +309,7 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
     }
   }
   if (MODE == MODE_FLUX) return;
-  __syncthreads();
+  wave_sync();
   const int i = c0 + lane;
   double rs[NPART];
 #pragma unroll
@@ -321,55 +334,62 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
 }
 
 // ---------------------------------------------------------------------------
-// y-sweep (2D): a block of four wavefronts owns 64 columns (one per lane,
-// coalesced) and a tile of a.ytile rows (chosen on the host so that one round
-// of resident blocks covers the grid), and marches down it four interface
-// rows at a time, one row per wavefront.  The records of the nine cell rows
-// the four stencils touch sit in an LDS ring; each iteration every
-// wavefront builds one new row (its global loads are issued an iteration
-// ahead), and the four interface fluxes meet in LDS for the conservative
-// difference, which MODE_STAGE combines with L_x into the RK3 stage.
+// y-sweep (2D): a block of four wavefronts owns 64 columns and a tile of
+// a.ytile rows (chosen on the host so that one round of resident blocks
+// covers the grid).  Each wavefront marches down its own YS_COLS columns,
+// YS_ROWS interface rows per step (lane = YS_COLS * row + column, so every
+// global access covers whole 128-byte row segments).  The records of the
+// YS_ROWS + 5 cell rows one step's stencils touch sit in a private LDS
+// ring; a step loads the next YS_ROWS cell rows, computes its fluxes, writes
+// the conservative differences (combined with L_x into the RK3 stage in
+// MODE_STAGE) and only then turns the loaded rows into records in the slots
+// of the rows no later stencil needs.  Wavefronts never wait for each other.
 // ---------------------------------------------------------------------------
 constexpr int YS_TILE_MIN = 16;
-constexpr int YS_RING = 9;
+constexpr int YS_COLS = 16;
+constexpr int YS_ROWS = 64 / YS_COLS;
+constexpr int YS_RING = YS_ROWS + 5;
+constexpr int YS_FSLOT = YS_ROWS + 1;
 
 template <int SYS, int M, class T, int MODE, int WV>
 __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>& cfg, int bx, int by, int gx) {
   if (a.check_active && !a.ctl->active) return;
   constexpr int NF = NumFields<SYS, M>::value;
-  __shared__ T ring[YS_RING * NF * 64];
-  __shared__ double fb[2][4][M][64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int RS = NF * YS_COLS + 32 / (int)sizeof(T);   // ring row stride, padded by 32 bytes
+  __shared__ T ring[4][YS_RING * RS];
+  __shared__ double fb[4][YS_FSLOT][M][YS_COLS];
+  const int lane = threadIdx.x & 63, wv = wave_id();
+  const int cl = lane % YS_COLS, g = lane / YS_COLS;
   const int nx = a.g.nx, ny = a.g.ny;
-  const int x = bx * 64 + lane;
+  const int x = bx * 64 + wv * YS_COLS + cl;
   const bool xin = x < nx;
   const int y0 = by * a.ytile;
   const int ylast = min(y0 + a.ytile, ny);   // cells [y0, ylast)
   const int kend = ylast;                    // interfaces y0 .. kend
   const size_t cs = (size_t)nx * ny;
   const double* col = a.q + (xin ? x : 0);
-  auto slot = [&](int r) { return (r - y0 + 3) % YS_RING; };
-  auto stage_row = [&](int r) {
+  T* const rw = &ring[wv][cl];
+  double(*const fw)[M][YS_COLS] = fb[wv];
+  auto slot = [&](int r) { return (r - y0 + 3) % YS_RING; };     // r >= y0 - 3
+  auto fslot = [&](int k) { return (k - y0 + 1) % YS_FSLOT; };   // k >= y0 - 1
+  // rows y0-3 .. y0+YS_ROWS+1 for the first step
+  for (int i = g; i < YS_RING; i += YS_ROWS) {
     if (xin) {
-      const size_t off = (size_t)bc_map(r, ny, a.g.bc_y) * nx;
-      stage_cell<SYS, M, 1, T>(col, cs, off, a.ph, &ring[slot(r) * NF * 64 + lane], 64);
+      const int r = y0 - 3 + i;
+      stage_cell<SYS, M, 1, T>(col, cs, (size_t)bc_map(r, ny, a.g.bc_y) * nx, a.ph, rw + slot(r) * RS, YS_COLS);
     }
-  };
-  // rows y0-3 .. y0+5 for the first iteration
-  stage_row(y0 - 3 + wv);
-  stage_row(y0 + 1 + wv);
-  if (wv == 0) stage_row(y0 + 5);
-  __syncthreads();
+  }
+  wave_sync();
   double rs[NPART];
 #pragma unroll
   for (int t = 0; t < NPART; ++t) rs[t] = 0.0;
-  const int nit = (kend - y0) / 4 + 1;
-  for (int it = 0; it < nit; ++it) {
-    const int k0 = y0 + 4 * it;
-    const int k = k0 + wv;
-    const bool act = k <= kend;
-    // prefetch the row this wavefront adds to the ring for the next iteration
-    const int rn = k0 + 6 + wv;
+  const int nst = (kend - y0) / YS_ROWS + 1;
+  for (int st = 0; st < nst; ++st) {
+    const int k0 = y0 + YS_ROWS * st;
+    const int k = k0 + g;
+    const bool act = k <= kend && xin;
+    // the cell row this lane adds for the next step's stencils
+    const int rn = k0 + YS_ROWS + 2 + g;
     const bool need = rn <= kend + 2 && xin;
     double qp[M];
     if (need) {
@@ -377,29 +397,27 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
 #pragma unroll
       for (int c = 0; c < M; ++c) qp[c] = col[off + c * cs];
     }
-    T F[M];
-    if (act && xin) {
+    if (act) {
+      T F[M];
       int off[6];
 #pragma unroll
-      for (int j = 0; j < 6; ++j) off[j] = slot(k - 3 + j) * NF * 64;
-      stencil_flux<SYS, M, 1, T, WV>(&ring[lane], 64, off, a.ph, a.ctl, cfg.w, F);
+      for (int j = 0; j < 6; ++j) off[j] = slot(k - 3 + j) * RS;
+      stencil_flux<SYS, M, 1, T, WV>(rw, YS_COLS, off, a.ph, a.ctl, cfg.w, F);
 #pragma unroll
-      for (int c = 0; c < M; ++c) fb[it & 1][wv][c][lane] = (double)F[c];
+      for (int c = 0; c < M; ++c) fw[fslot(k)][c][cl] = (double)F[c];
       if (MODE == MODE_FLUX && (k < kend || k == ny)) {
 #pragma unroll
         for (int c = 0; c < M; ++c) a.out[(size_t)c * (ny + 1) * nx + (size_t)k * nx + x] = (double)F[c];
       }
     }
-    __syncthreads();
-    const int r = k - 1;   // cell row finished by this wavefront
-    if (MODE != MODE_FLUX && act && xin && r >= y0 && r < ylast) {
+    wave_sync();
+    const int r = k - 1;   // cell row finished by this lane
+    if (MODE != MODE_FLUX && act && r >= y0 && r < ylast) {
       const size_t idx = (size_t)r * nx + x;
       double qnew[M];
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        const double fk = fb[it & 1][wv][c][lane];
-        const double fm = wv > 0 ? fb[it & 1][wv - 1][c][lane] : fb[(it - 1) & 1][3][c][lane];
-        const double L = -(fk - fm) * a.g.inv_dy;
+        const double L = -(fw[fslot(k)][c][cl] - fw[fslot(k - 1)][c][cl]) * a.g.inv_dy;
         const size_t o = c * cs + idx;
         if (MODE == MODE_RHS) {
           a.out[o] = a.lx[o] + L;
@@ -412,9 +430,9 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
       if (MODE == MODE_STAGE) cell_speeds<SYS, M>(qnew, a.ph, rs);
     }
     if (need) {
-      // the slot of row rn held row rn - 9 = k0 - 3 + wv, read for the last
-      // time before the barrier above
-      T* rec = &ring[slot(rn) * NF * 64 + lane];
+      // row rn takes the slot of row rn - YS_RING = k0 - 3 + g, which only
+      // this step's stencils (above the synchronisation) read
+      T* rec = rw + slot(rn) * RS;
       if (SYS == SYS_EULER) {
         double qd[M];
         if (M == 4) { qd[0] = qp[0]; qd[1] = qp[2 % M]; qd[2 % M] = qp[1]; qd[3 % M] = qp[3 % M]; }
@@ -422,14 +440,14 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
 #pragma unroll
           for (int c = 0; c < M; ++c) qd[c] = qp[c];
         }
-        euler_record<T, (M == 1 ? 4 : M)>(*reinterpret_cast<const double(*)[(M == 1 ? 4 : M)]>(qd), (T)a.ph.gm1, rec, 64);
+        euler_record<T, (M == 1 ? 4 : M)>(*reinterpret_cast<const double(*)[(M == 1 ? 4 : M)]>(qd), (T)a.ph.gm1, rec, YS_COLS);
       } else {
         const T u = (T)qp[0];
         rec[0] = u;
-        rec[64] = scalar_f<SYS, T>(u, (T)a.ph.adv[1]);
+        rec[YS_COLS] = scalar_f<SYS, T>(u, (T)a.ph.adv[1]);
       }
     }
-    __syncthreads();
+    wave_sync();
   }
   if (MODE == MODE_STAGE && a.part)
     block_max_store(rs, a.part + ((size_t)by * gx + bx) * NPART);

@@ -283,15 +283,18 @@ static int pick_ytile(za_ctx* c) {
   const void* fn = p.system == ZA_EULER
                        ? reinterpret_cast<const void*>(&k_sweep_y<SYS_EULER, 4, T, MODE_STAGE, WV_Z1>)
                        : reinterpret_cast<const void*>(&k_sweep_y<SYS_ADV, 1, T, MODE_STAGE, WV_Z1>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, fn, 256, 0) != hipSuccess || blocks_per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, fn, 256, 0) != hipSuccess ||
+      blocks_per_cu < 1)
     blocks_per_cu = 2;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
     cus = 256;
   const long long strips = (p.nx + 63) / 64;
   const long long slots = (long long)blocks_per_cu * cus;
   long long tiles = std::max<long long>(1, slots / strips);
-  int rows = (int)((p.ny + tiles - 1) / tiles);
-  rows = (rows + 3) / 4 * 4;
+  // a tile of R rows computes R + 1 interface rows, YS_ROWS per step: take
+  // the largest R with as many steps as the rows a tile needs
+  const int need = (int)((p.ny + tiles - 1) / tiles);
+  const int rows = YS_ROWS * ((need + YS_ROWS) / YS_ROWS) - 1;
   return std::max(rows, YS_TILE_MIN);
 }
 

@@ -36,7 +36,7 @@ using namespace za;
 
 constexpr int MAX_SLOTS = 256;  // per class
 constexpr int NCLASS = 4;       // (1D, 2D) x (FP64, FP32 reconstruction)
-constexpr int SERVE_YTILE = 32; // y-sweep rows per block in batches
+constexpr int SERVE_YTILE = 8 * YS_ROWS - 1; // y-sweep rows per block in batches (a whole number of steps)
 
 struct SlotDesc {
   double* st;        // the request's state (Q^n, then the result)
