@@ -9,7 +9,7 @@ enum Sys { SYS_ADV = 0, SYS_EULER = 1, SYS_BURGERS = 2, SYS_BUCKLEY = 3 };
 enum Mode {
   MODE_FLUX = 0,    // write the interface fluxes
   MODE_RHS = 1,     // write (x) / accumulate (y) L
-  MODE_LX = 2,      // 2D stage, x-sweep: write L_x to workspace
+  MODE_LX = 2,      // 2D stage, x-sweep: write ca Q^n + cb (Q + dt L_x) to workspace
   MODE_STAGE = 3    // last sweep of a stage: L (+ L_x) -> RK3 stage update
 };
 
@@ -241,14 +241,14 @@ __device__ __forceinline__ void stencil_flux(const T* __restrict__ rec, int fs, 
 struct SweepArgs {
   const double* q;       // sweep input Q^(s)
   const double* qn;      // Q^n (stage update)
-  const double* lx;      // L_x (2D stage / rhs accumulate)
+  const double* lx;      // 2D: L_x (rhs) or the x-sweep's partial stage update
   double* out;           // L, L_x, Q^(s+1) or fluxes
   DevCtl* ctl;
   Geom g;
   Phys ph;
   double ca, cb;         // stage: out = ca*qn + cb*(q + dt*L)
   int check_active;      // stepping: skip when the integration is inactive
-  int ytile;             // y-sweep rows per block (multiple of 4)
+  int ytile;             // y-sweep: at most this many rows per block (band)
   double* part;          // MODE_STAGE: per-block wave-speed maxima of the new state
 };
 
@@ -316,34 +316,65 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
   for (int t = 0; t < NPART; ++t) rs[t] = 0.0;
   if (live && lane < XS_CELLS && i < nx) {
     const size_t idx = row + i;
-    double qnew[M];
+    if (MODE == MODE_LX) {
+      // partial stage ca Q^n + cb (Q + dt L_x); FP64 records hold Q exactly
+      double qc[M], qb[M];
 #pragma unroll
-    for (int c = 0; c < M; ++c) {
-      const double L = -(fl[wv][c][lane + 1] - fl[wv][c][lane]) * a.g.inv_dx;
-      const size_t o = c * cs + idx;
-      if (MODE == MODE_RHS || MODE == MODE_LX) {
-        a.out[o] = L;
-      } else {  // MODE_STAGE (1D)
-        qnew[c] = fma(a.ca, a.qn[o], a.cb * fma(a.ctl->dt, L, a.q[o]));
-        a.out[o] = qnew[c];
+      for (int c = 0; c < M; ++c) {
+        if (sizeof(T) == sizeof(double) && SYS == SYS_EULER) {
+          typedef RecLayout<(M == 1 ? 4 : M)> Lo;
+          const int f = c == 0 ? (int)Lo::Q0 : (c == M - 1 ? (int)Lo::E : (c == 1 ? (int)Lo::Q1 : (int)Lo::Q2));
+          qc[c] = (double)xr[wv][f * XS_REC + lane + 3];
+        } else if (sizeof(T) == sizeof(double)) {
+          qc[c] = (double)xr[wv][lane + 3];
+        } else {
+          qc[c] = a.q[c * cs + idx];
+        }
       }
+      if (a.ca != 0.0) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) qb[c] = a.qn[c * cs + idx];
+      } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) qb[c] = 0.0;
+      }
+      const double dt = a.ctl->dt;
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const double L = -(fl[wv][c][lane + 1] - fl[wv][c][lane]) * a.g.inv_dx;
+        a.out[c * cs + idx] = fma(a.ca, qb[c], a.cb * fma(dt, L, qc[c]));
+      }
+    } else {
+      double qnew[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const double L = -(fl[wv][c][lane + 1] - fl[wv][c][lane]) * a.g.inv_dx;
+        const size_t o = c * cs + idx;
+        if (MODE == MODE_RHS) {
+          a.out[o] = L;
+        } else {  // MODE_STAGE (1D)
+          qnew[c] = fma(a.ca, a.qn[o], a.cb * fma(a.ctl->dt, L, a.q[o]));
+          a.out[o] = qnew[c];
+        }
+      }
+      if (MODE == MODE_STAGE) cell_speeds<SYS, M>(qnew, a.ph, rs);
     }
-    if (MODE == MODE_STAGE) cell_speeds<SYS, M>(qnew, a.ph, rs);
   }
   if (MODE == MODE_STAGE && a.part) block_max_store(rs, a.part + (size_t)bid * NPART);
 }
 
 // ---------------------------------------------------------------------------
-// y-sweep (2D): a block of four wavefronts owns 64 columns and a tile of
-// a.ytile rows (chosen on the host so that one round of resident blocks
+// y-sweep (2D): a block of four wavefronts owns 64 columns and a band of at
+// most a.ytile rows (chosen on the host so that one round of resident blocks
 // covers the grid).  Each wavefront marches down its own YS_COLS columns,
 // YS_ROWS interface rows per step (lane = YS_COLS * row + column, so every
 // global access covers whole 128-byte row segments).  The records of the
 // YS_ROWS + 5 cell rows one step's stencils touch sit in a private LDS
 // ring; a step loads the next YS_ROWS cell rows, computes its fluxes, writes
-// the conservative differences (combined with L_x into the RK3 stage in
-// MODE_STAGE) and only then turns the loaded rows into records in the slots
-// of the rows no later stencil needs.  Wavefronts never wait for each other.
+// the conservative differences (in MODE_STAGE added to the x-sweep's partial
+// update, which completes the RK3 stage) and only then turns the loaded rows
+// into records in the slots of the rows no later stencil needs.  Wavefronts
+// never wait for each other.
 // ---------------------------------------------------------------------------
 constexpr int YS_TILE_MIN = 16;
 constexpr int YS_COLS = 16;
@@ -351,9 +382,25 @@ constexpr int YS_ROWS = 64 / YS_COLS;
 constexpr int YS_RING = YS_ROWS + 5;
 constexpr int YS_FSLOT = YS_ROWS + 1;
 
+// Issue priority of a wavefront that has done step st of nst: it falls as the
+// wavefront advances, so each SIMD favours the wavefronts that are behind and
+// all of them finish at about the same time.  (Among equal priorities the
+// oldest wavefront issues first, which would finish the first-dispatched
+// tiles early and leave the last ones running alone at the end.)
+__device__ __forceinline__ void progress_prio(int st, int nst) {
+  const int q = (4 * st) / nst;
+  if (q == 0) __builtin_amdgcn_s_setprio(3);
+  else if (q == 1) __builtin_amdgcn_s_setprio(2);
+  else if (q == 2) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+}
+
+// One wavefront's tile: columns x0 .. x0+YS_COLS-1, cell rows [y0, ylast)
+// (interfaces y0 .. ylast).  MODE_STAGE folds the wave speeds of the new
+// states into rs.
 template <int SYS, int M, class T, int MODE, int WV>
-__device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>& cfg, int bx, int by, int gx) {
-  if (a.check_active && !a.ctl->active) return;
+__device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>& cfg, int x0, int y0, int ylast,
+                                             double (&rs)[NPART]) {
   constexpr int NF = NumFields<SYS, M>::value;
   constexpr int RS = NF * YS_COLS + 32 / (int)sizeof(T);   // ring row stride, padded by 32 bytes
   __shared__ T ring[4][YS_RING * RS];
@@ -361,10 +408,8 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
   const int lane = threadIdx.x & 63, wv = wave_id();
   const int cl = lane % YS_COLS, g = lane / YS_COLS;
   const int nx = a.g.nx, ny = a.g.ny;
-  const int x = bx * 64 + wv * YS_COLS + cl;
+  const int x = x0 + cl;
   const bool xin = x < nx;
-  const int y0 = by * a.ytile;
-  const int ylast = min(y0 + a.ytile, ny);   // cells [y0, ylast)
   const int kend = ylast;                    // interfaces y0 .. kend
   const size_t cs = (size_t)nx * ny;
   const double* col = a.q + (xin ? x : 0);
@@ -380,11 +425,9 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
     }
   }
   wave_sync();
-  double rs[NPART];
-#pragma unroll
-  for (int t = 0; t < NPART; ++t) rs[t] = 0.0;
   const int nst = (kend - y0) / YS_ROWS + 1;
   for (int st = 0; st < nst; ++st) {
+    progress_prio(st, nst);
     const int k0 = y0 + YS_ROWS * st;
     const int k = k0 + g;
     const bool act = k <= kend && xin;
@@ -421,9 +464,8 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
         const size_t o = c * cs + idx;
         if (MODE == MODE_RHS) {
           a.out[o] = a.lx[o] + L;
-        } else {  // MODE_STAGE
-          const double Lt = a.lx[o] + L;
-          qnew[c] = fma(a.ca, a.qn[o], a.cb * fma(a.ctl->dt, Lt, a.q[o]));
+        } else {  // MODE_STAGE: the x-sweep left ca Q^n + cb (Q + dt L_x)
+          qnew[c] = fma(a.cb * a.ctl->dt, L, a.lx[o]);
           a.out[o] = qnew[c];
         }
       }
@@ -449,6 +491,20 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
     }
     wave_sync();
   }
+}
+
+// Block (bx, by) owns 64 columns, one YS_COLS-column tile per wavefront, and
+// band by of the ceil(ny / ytile) bands of (near) equal height.
+template <int SYS, int M, class T, int MODE, int WV>
+__device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>& cfg, int bx, int by, int gx) {
+  if (a.check_active && !a.ctl->active) return;
+  double rs[NPART];
+#pragma unroll
+  for (int t = 0; t < NPART; ++t) rs[t] = 0.0;
+  const int ny = a.g.ny;
+  const int nb = (ny + a.ytile - 1) / a.ytile;
+  const int y0 = (int)((long long)by * ny / nb), ylast = (int)((long long)(by + 1) * ny / nb);
+  sweep_y_tile<SYS, M, T, MODE, WV>(a, cfg, bx * 64 + wave_id() * YS_COLS, y0, ylast, rs);
   if (MODE == MODE_STAGE && a.part)
     block_max_store(rs, a.part + ((size_t)by * gx + bx) * NPART);
 }
@@ -472,6 +528,7 @@ template <int SYS, int M, class T, int MODE, int WV>
 __global__ __launch_bounds__(256) void k_sweep_y_any(SweepArgs a, CfgArg<T> cfg) {
   sweep_y_body<SYS, M, T, MODE, WV>(a, cfg, blockIdx.x, blockIdx.y, gridDim.x);
 }
+
 
 enum FinalKind { FIN_RHS = 0, FIN_STAGE0 = 1, FIN_STAGEK = 2 };
 
