@@ -33,11 +33,13 @@ struct WeightCfg {
 // linear weights) decided at run time.
 enum { WV_Z1 = 0, WV_GENERAL = 1 };
 
-// Reciprocal and quotient from the hardware reciprocal estimate refined by
-// two Newton-Raphson steps (r <- r + r (1 - x r)), then one residual
-// correction of the quotient (q <- q + r (a - x q)).  Operands stay far from
-// the denormal and overflow ranges here (positive normal densities and
-// weight sums >= 1e-156), so no exponent scaling is needed.
+// Reciprocal from the hardware reciprocal estimate refined by two
+// Newton-Raphson steps (r <- r + r (1 - x r)); quotient from an estimate
+// refined once, then one residual correction (q <- q + r (a - x q)), which
+// squares the relative error of the once-refined reciprocal again (an
+// estimate good to 2^-14 already leaves only the final rounding).  Operands
+// stay far from the denormal and overflow ranges here (positive normal
+// densities and weight sums >= 1e-156), so no exponent scaling is needed.
 __device__ __forceinline__ double rcp_nr(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
@@ -46,7 +48,8 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, e, r);
 }
 __device__ __forceinline__ double div_nr(double a, double x) {
-  const double r = rcp_nr(x);
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
   const double q = a * r;
   return fma(fma(-x, q, a), r, q);
 }
@@ -128,13 +131,29 @@ __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const Weigh
   const T g2 = fma(T(3), d2, -d3);       // -(3 s2 - 4 s3 + s4)
   const T g3 = fma(T(5), d3, T(-3) * d4);// -5 s3 + 8 s4 - 3 s5
   const T k133 = T(13) / T(3);
+  const T t5 = (e3 - e0) + T(3) * (e1 - e2);   // fifth difference
+  const T t2 = t5 + t5;
+  if (WV == WV_Z1 && sizeof(T) == sizeof(double)) {
+    // b_k = B_k + 16 eps with the epsilon folded into the sum of squares;
+    // the mean of the four b's then carries it too
+    const T b0 = fma(k133 * e0, e0, fma(g0, g0, w.eps16));
+    const T b1 = fma(k133 * e1, e1, fma(g1, g1, w.eps16));
+    const T b2 = fma(k133 * e2, e2, fma(g2, g2, w.eps16));
+    const T bd = fma(k133 * e3, e3, fma(g3, g3, w.eps16));
+    const T b3 = T(0.25) * ((b0 + b1) + (b2 + bd));
+    const T tau = t2 * t2;
+    const T p01 = b0 * b1, p23 = b2 * b3;
+    const T w0 = (b0 + tau) * (b1 * p23);
+    const T v1 = (b1 + tau) * (b0 * p23);   // w_1 / 9
+    const T v2 = (b2 + tau) * (p01 * b3);   // w_2 / 9
+    const T w3 = (b3 + tau) * (p01 * b2);
+    return div_nr(fma(w0, q0, fma(T(9), fma(v1, q1, v2 * q2), w3 * q3)), fma(T(9), v1 + v2, w0 + w3));
+  }
   T B0 = fma(k133 * e0, e0, g0 * g0);
   T B1 = fma(k133 * e1, e1, g1 * g1);
   T B2 = fma(k133 * e2, e2, g2 * g2);
   const T Bd = fma(k133 * e3, e3, g3 * g3);
   T B3 = T(0.25) * ((B0 + B1) + (B2 + Bd));
-  const T t5 = (e3 - e0) + T(3) * (e1 - e2);   // fifth difference
-  const T t2 = t5 + t5;
   T tau = t2 * t2;
   T eps = w.eps16;
   if (WV == WV_GENERAL && w.ai) {
@@ -146,22 +165,12 @@ __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const Weigh
     eps = w.eps4;
   }
   const T b0 = B0 + eps, b1 = B1 + eps, b2 = B2 + eps, b3 = B3 + eps;
-  if (WV == WV_GENERAL || sizeof(T) == 4) {
-    T g0w = tau * rcp_nr(b0), g1w = tau * rcp_nr(b1), g2w = tau * rcp_nr(b2), g3w = tau * rcp_nr(b3);
-    if (WV == WV_GENERAL && w.p != T(1)) {
-      g0w = pow(g0w, w.p); g1w = pow(g1w, w.p); g2w = pow(g2w, w.p); g3w = pow(g3w, w.p);
-    }
-    const T a0 = T(1) + g0w, a1 = T(9) * (T(1) + g1w), a2 = T(9) * (T(1) + g2w), a3 = T(1) + g3w;
-    return div_nr(fma(a0, q0, fma(a1, q1, fma(a2, q2, a3 * q3))), (a0 + a1) + (a2 + a3));
-  } else {
-    const T p01 = b0 * b1, p23 = b2 * b3;
-    const T n01 = T(9) * p01, n23 = T(9) * p23;
-    const T w0 = (b0 + tau) * (b1 * p23);
-    const T w1 = (b1 + tau) * (b0 * n23);
-    const T w2 = (b2 + tau) * (n01 * b3);
-    const T w3 = (b3 + tau) * (p01 * b2);
-    return div_nr(fma(w0, q0, fma(w1, q1, fma(w2, q2, w3 * q3))), (w0 + w1) + (w2 + w3));
+  T g0w = tau * rcp_nr(b0), g1w = tau * rcp_nr(b1), g2w = tau * rcp_nr(b2), g3w = tau * rcp_nr(b3);
+  if (WV == WV_GENERAL && w.p != T(1)) {
+    g0w = pow(g0w, w.p); g1w = pow(g1w, w.p); g2w = pow(g2w, w.p); g3w = pow(g3w, w.p);
   }
+  const T a0 = T(1) + g0w, a1 = T(9) * (T(1) + g1w), a2 = T(9) * (T(1) + g2w), a3 = T(1) + g3w;
+  return div_nr(fma(a0, q0, fma(a1, q1, fma(a2, q2, a3 * q3))), (a0 + a1) + (a2 + a3));
 }
 
 // Both Lax-Friedrichs halves of one characteristic field at one interface
