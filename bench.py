@@ -51,10 +51,48 @@ def sweep_flops(nx, ny, d):
 
 
 def sweep_bytes(nx, ny, d):
-    """Algorithmic HBM bytes of one sweep launch: x reads Q and writes L_x;
-    y reads Q, L_x and Q^n and writes the new stage state (FP64, m = 4)."""
+    """Algorithmic HBM bytes of one sweep launch, averaged over the three RK3
+    stages (FP64, m = 4, 32 B per cell and array): the x-sweep reads Q (and
+    Q^n in stages 2 and 3) and writes the partial stage ca Q^n + cb (Q + dt
+    L_x); the y-sweep reads Q and that partial stage and writes Q^(s+1)."""
     cells = nx * ny
-    return cells * 32 * (2 if d == "x" else 4)
+    return cells * 32 * 8 // 3 if d == "x" else cells * 32 * 3
+
+
+# Measured HBM traffic of the dominant kernel (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, scaled by the same counters on a plain copy): valid only while
+# the kernel sources hash to the value recorded next to the figure.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_y_2d_euler_2048_fp64_traffic.md")
+KERNEL_SOURCES = ("za_device.hpp", "za_kernels.hpp", "za_lib.hip")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2603_26272_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """Bytes per launch recorded for `kernel`, or None if absent or stale."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    rec = {}
+    for ln in lines:
+        if ":" in ln and ln.startswith("- "):
+            k, v = ln[2:].split(":", 1)
+            rec[k.strip()] = v.strip().strip("`")
+    if rec.get("kernel") != kernel or rec.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    try:
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def run_gpu(P, q0_np, steps, warmup, torch, Context):
@@ -333,7 +371,7 @@ def main():
     fl = sweep_flops(nx, ny, d)
     achieved = fl / (avg_ms[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(f"k_sweep_{d}"),
                 "kernel": f"k_sweep_{d} (2D Euler FP64)",
                 "avg_launch_ms": avg_ms[dom], "launches": counts[dom],
                 "algorithmic_flop_per_launch": fl,
