@@ -39,6 +39,7 @@ class _Problem(C.Structure):
         ("mu0", C.c_double),
         ("lf", C.c_int32),
         ("linear_weights", C.c_int32),
+        ("order", C.c_int32),
     ]
 
 
@@ -84,6 +85,11 @@ def lib():
         L.orc_euler_eigen.restype = None
         L.orc_euler_eigen.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                       C.c_double, C.c_double, _DP, _DP]
+        L.orc_set_order_tables.restype = C.c_int
+        L.orc_set_order_tables.argtypes = [C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int]
+        L.orc_recon_r.restype = C.c_double
+        L.orc_recon_r.argtypes = [C.c_int, _DP, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int,
+                                  C.c_int, _DP]
         L.orc_set_threads.restype = None
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_get_threads.restype = C.c_int
@@ -119,7 +125,26 @@ def _problem(pb) -> _Problem:
     P.mu0 = float(_get(pb, "mu0", 1e-40))
     P.lf = int(_get(pb, "lf", 0))
     P.linear_weights = int(_get(pb, "linear_weights", 0))
+    P.order = int(_get(pb, "order", 3))
+    _ensure_order(P.order)
     return P
+
+
+_orders_set = set()
+
+
+def _ensure_order(r: int) -> None:
+    """Hand the exact tables of the order-2r scheme to the C oracle once."""
+    if r in _orders_set or not (2 <= r <= 6):
+        return
+    from . import coeffs
+    pairs = coeffs.flat_rationals(r)
+    n = len(pairs)
+    num = (C.c_int64 * n)(*[a for a, _ in pairs])
+    den = (C.c_int64 * n)(*[b for _, b in pairs])
+    if lib().orc_set_order_tables(int(r), num, den, n) != 0:
+        raise RuntimeError(f"oracle rejected the order-{2 * r} tables")
+    _orders_set.add(r)
 
 
 def _ptr(a: np.ndarray):
@@ -149,6 +174,21 @@ def recon(v6, p=1.0, eps=1e-40, ai=0, mu0=1e-40, linear=0, detail=False):
         return r, {"q": d[0:4].copy(), "beta": d[4:9].copy(), "tau": d[9], "mu": d[10],
                    "omega": d[11:15].copy()}
     return lib().orc_recon(_ptr(v), p, eps, ai, mu0, linear, None)
+
+
+def recon_r(r, v, p=1.0, eps=1e-40, ai=0, mu0=1e-40, linear=0, prec=0, detail=False):
+    """O1 for the order-2r scheme from v = (f_{i-r+1}, .., f_{i+r}); prec 0 FP64,
+    1 FP32, 2 quad (rounded to FP64)."""
+    _ensure_order(int(r))
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert v.shape == (2 * r,)
+    if detail:
+        d = np.zeros(3 * r + 6)
+        out = lib().orc_recon_r(int(r), _ptr(v), p, eps, ai, mu0, linear, prec, _ptr(d))
+        return out, {"q": d[0:r + 1].copy(), "beta": d[r + 1:2 * r + 1].copy(), "beta_d": d[2 * r + 1],
+                     "beta_r": d[2 * r + 2], "tau": d[2 * r + 3], "mu": d[2 * r + 4],
+                     "omega": d[2 * r + 5:3 * r + 6].copy()}
+    return lib().orc_recon_r(int(r), _ptr(v), p, eps, ai, mu0, linear, prec, None)
 
 
 def recon_f32(v6, p=1.0, eps=1e-20, ai=0, mu0=1e-8, linear=0):

@@ -35,6 +35,7 @@
 #include <cstdint>
 #include <cstring>
 #include <cstdlib>
+#include <memory>
 #include <vector>
 #include <algorithm>
 #include <quadmath.h>
@@ -257,6 +258,149 @@ static R recon_za6(const R v[6], const ZA6Const<R>& K, const ReconParams& P,
 }
 
 /* ------------------------------------------------------------------------ */
+/* O1 for any even order 2r (Section 2, Section 3, Appendix A).              */
+/* The tables are exact rationals derived from the definitions by            */
+/* oracle/coeffs.py (pinned there against the printed tables) and handed     */
+/* over once per order through orc_set_order_tables.                         */
+/* ------------------------------------------------------------------------ */
+enum { R_MAX = 6 };
+struct GenTab { int set; std::vector<long long> num, den; };
+static GenTab g_gen[R_MAX + 1];
+
+template <class R> struct GenConst {
+  int r;
+  R ck[R_MAX + 1][R_MAX];                 /* c_k on S_k, k = 0..r            */
+  R d[R_MAX + 1];                         /* ideal weights                   */
+  R ctau[2 * R_MAX];                      /* (2r-1)-th difference            */
+  R D[R_MAX + 1][R_MAX][R_MAX][R_MAX];    /* D[k][l][m][j]: coefficient of   */
+                                          /* xi^m in p_k^(l), from f_j       */
+  R I[2 * R_MAX];                         /* int_{-1/2}^{1/2} xi^s           */
+  explicit GenConst(int rr) : r(rr) {
+    const GenTab& T = g_gen[rr];
+    size_t at = 0;
+    auto next = [&]() { R v = R((double)T.num[at]) / R((double)T.den[at]); ++at; return v; };
+    for (int k = 0; k <= r; ++k)
+      for (int j = 0; j < r; ++j) ck[k][j] = next();
+    for (int k = 0; k <= r; ++k) d[k] = next();
+    for (int j = 0; j < 2 * r; ++j) ctau[j] = next();
+    for (int k = 0; k <= r; ++k)
+      for (int l = 1; l < r; ++l)
+        for (int m = 0; m < r - l; ++m)
+          for (int j = 0; j < r; ++j) D[k][l][m][j] = next();
+    for (int s2 = 0; s2 <= 2 * r - 4; ++s2) I[s2] = next();
+  }
+};
+
+/* Reconstruct h at x_{i+1/2} from v[0..2r-1] = (f_{i-r+1}, .., f_{i+r}).
+ * det (optional) receives q[0..r], beta_0..beta_{r-1}, beta_d, beta_r (the
+ * mean), tau, mu, omega[0..r]: 3r + 6 values. */
+template <class R>
+static R recon_gen(const R* v, const GenConst<R>& K, const ReconParams& P, double* det) {
+  const int r = K.r;
+  /* candidates q_k = <c_k, f_k>, S_k = cells i-r+1+k .. i+k */
+  R q[R_MAX + 1];
+  for (int k = 0; k <= r; ++k) {
+    R acc = R(0);
+    for (int j = 0; j < r; ++j) acc = acc + K.ck[k][j] * v[k + j];
+    q[k] = acc;
+  }
+  R out = R(0);
+  if (P.linear) {
+    for (int k = 0; k <= r; ++k) out = out + K.d[k] * q[k];
+    return out;
+  }
+  /* eq:SI: beta = sum_l int_{I_i} (p_k^(l))^2, written with the
+   * coefficients a_m of p_k^(l) (linear in f) and the interval moments. */
+  R beta[R_MAX + 2];
+  for (int k = 0; k <= r; ++k) {
+    R b = R(0);
+    for (int l = 1; l < r; ++l) {
+      R a[R_MAX];
+      const int nm = r - l;
+      for (int m = 0; m < nm; ++m) {
+        R acc = R(0);
+        for (int j = 0; j < r; ++j) acc = acc + K.D[k][l][m][j] * v[k + j];
+        a[m] = acc;
+      }
+      for (int m1 = 0; m1 < nm; ++m1)
+        for (int m2 = 0; m2 < nm; ++m2)
+          if ((m1 + m2) % 2 == 0) b = b + K.I[m1 + m2] * (a[m1] * a[m2]);
+    }
+    beta[k] = b;
+  }
+  /* beta[r] is beta_d; the downwind substencil takes the mean of the r
+   * upwind indicators and beta_d (eq:SI_downwind) */
+  R sum = R(0);
+  for (int k = 0; k <= r; ++k) sum = sum + beta[k];
+  const R beta_d = beta[r];
+  const R beta_r = sum / R(r + 1);
+  R bw[R_MAX + 1];
+  for (int k = 0; k < r; ++k) bw[k] = beta[k];
+  bw[r] = beta_r;
+  /* tau = <c_tau, f^{2r}>^2 (eq:GSI) */
+  R t = R(0);
+  for (int j = 0; j < 2 * r; ++j) t = t + K.ctau[j] * v[j];
+  const R tau = t * t;
+  R mu = R(1);
+  if (P.ai) {
+    R mean = R(0);
+    for (int j = 0; j < 2 * r; ++j) mean = mean + v[j];
+    mean = mean / R(2 * r);
+    R sa = R(0);
+    for (int j = 0; j < 2 * r; ++j) sa = sa + r_abs(v[j] - mean);
+    mu = sa / R(2 * r) + R(P.mu0);
+  }
+  const R eps = R(P.eps);
+  const R epsmu2 = P.ai ? eps * (mu * mu) : eps;
+  R alpha[R_MAX + 1], asum = R(0);
+  for (int k = 0; k <= r; ++k) {
+    R g = tau / (bw[k] + epsmu2);
+    if (P.p != 1.0) g = r_pow(g, R(P.p));
+    alpha[k] = K.d[k] * (R(1) + g);
+    asum = asum + alpha[k];
+  }
+  R omega[R_MAX + 1];
+  for (int k = 0; k <= r; ++k) {
+    omega[k] = alpha[k] / asum;
+    out = out + omega[k] * q[k];
+  }
+  if (det) {
+    int o = 0;
+    for (int k = 0; k <= r; ++k) det[o++] = to_state(q[k]);
+    for (int k = 0; k < r; ++k) det[o++] = to_state(beta[k]);
+    det[o++] = to_state(beta_d);
+    det[o++] = to_state(beta_r);
+    det[o++] = to_state(tau);
+    det[o++] = to_state(mu);
+    for (int k = 0; k <= r; ++k) det[o++] = to_state(omega[k]);
+  }
+  return out;
+}
+
+/* The scheme of one sweep: r = 3 takes the sixth-order routine above,
+ * other orders the generic one. */
+template <class R> struct Scheme {
+  int r;
+  ZA6Const<R> k6;
+  const GenConst<R>* kg;
+  R operator()(const R* v, const ReconParams& P) const {
+    return r == 3 ? recon_za6<R>(v, k6, P, nullptr) : recon_gen<R>(v, *kg, P, nullptr);
+  }
+};
+
+/* Owns the generic tables of one order in type R (built before any parallel
+ * region, read-only inside). */
+template <class R> struct SchemeFor {
+  std::unique_ptr<GenConst<R>> g;
+  Scheme<R> S;
+  explicit SchemeFor(int r) {
+    if (r != 3) g.reset(new GenConst<R>(r));
+    S.r = r;
+    S.kg = g.get();
+  }
+};
+
+/* ------------------------------------------------------------------------ */
 /* Problem description (the oracle's own; mirrors the library's fields).     */
 /* ------------------------------------------------------------------------ */
 enum { SYS_ADVECTION = 0, SYS_EULER = 1, SYS_BURGERS = 2, SYS_BUCKLEY = 3 };
@@ -279,6 +423,7 @@ typedef struct {
   double mu0;
   int32_t lf;
   int32_t linear_weights;
+  int32_t order;          /* r of the order-2r scheme (0 or 3: WENO-ZA6) */
 } orc_problem;
 }
 
@@ -435,50 +580,51 @@ static int wave_speeds(const orc_problem& P, const double* q, int dir, double* a
 /* ------------------------------------------------------------------------ */
 /* O2/O3: numerical fluxes of one sweep.                                      */
 /* Interface k (0..n) of a line of n cells sits at x_{k-1/2}, between cells   */
-/* k-1 and k; its six-point stencil is cells k-3 .. k+2.                      */
+/* k-1 and k; its 2r-point stencil is cells k-r .. k+r-1.                     */
 /* ------------------------------------------------------------------------ */
 template <class R>
-static void line_fluxes(const orc_problem& P, const ZA6Const<R>& K, const ReconParams& RP,
+static void line_fluxes(const orc_problem& P, const Scheme<R>& S, const ReconParams& RP,
                         int dir, const double* alpha, int n, int bc,
                         /* gather cell j (ghosts allowed) of this line into Q[m] */
                         const double* const* lineptr, size_t stride,
                         double* Fhat /* [m][n+1], stride n+1 */) {
   const int m = ncomp(P);
+  const int r = S.r, w = 2 * r;
   const R h = R(0.5);
-  /* physical flux of every cell including ghosts, f_j = f(Q_j) */
-  std::vector<R> Qc((size_t)(n + 6) * m), Fc((size_t)(n + 6) * m);
-  for (int j = -3; j < n + 3; ++j) {
+  /* physical flux of every cell including r ghosts per side, f_j = f(Q_j) */
+  std::vector<R> Qc((size_t)(n + 2 * r) * m), Fc((size_t)(n + 2 * r) * m);
+  for (int j = -r; j < n + r; ++j) {
     int jj = bc_index(j, n, bc);
-    R* Qj = &Qc[(size_t)(j + 3) * m];
-    R* Fj = &Fc[(size_t)(j + 3) * m];
+    R* Qj = &Qc[(size_t)(j + r) * m];
+    R* Fj = &Fc[(size_t)(j + r) * m];
     for (int c = 0; c < m; ++c) Qj[c] = from_state<R>(lineptr[c][(size_t)jj * stride]);
     if (P.system == SYS_EULER) euler_flux<R>(m, dir, R(P.gamma - 1), Qj, Fj);
     else Fj[0] = scalar_flux<R>(P, dir, Qj[0]);
   }
+  R vp[2 * R_MAX], vm[2 * R_MAX];
   for (int k = 0; k <= n; ++k) {
     if (P.system != SYS_EULER) {
       /* Global Lax-Friedrichs splitting f^(+-) = (f +- alpha Q)/2 (eq:LF),
-       * f^+ reconstructed from (f_{i-2..i+3}), f^- from the mirrored
-       * stencil (f_{i+3..i-2}); F = f^+ + f^-. */
+       * f^+ reconstructed from (f_{i-r+1..i+r}), f^- from the mirrored
+       * stencil (f_{i+r..i-r+1}); F = f^+ + f^-. */
       R a = from_state<R>(alpha[0]);
-      R vp[6], vm[6];
-      for (int j = 0; j < 6; ++j) {
-        const int cj = k - 3 + j;
-        R Qj = Qc[(size_t)(cj + 3)], Fj = Fc[(size_t)(cj + 3)];
+      for (int j = 0; j < w; ++j) {
+        const int cj = k - r + j;
+        R Qj = Qc[(size_t)(cj + r)], Fj = Fc[(size_t)(cj + r)];
         vp[j] = h * (Fj + a * Qj);
-        vm[5 - j] = h * (Fj - a * Qj);
+        vm[w - 1 - j] = h * (Fj - a * Qj);
       }
-      R fh = recon_za6<R>(vp, K, RP, nullptr) + recon_za6<R>(vm, K, RP, nullptr);
+      R fh = S(vp, RP) + S(vm, RP);
       Fhat[k] = to_state(fh);
       continue;
     }
     /* Characteristic-wise LF splitting for the Euler system (Section 4.2):
-     * Roe average of cells k-1 and k, project the six-point stencil of Q and
+     * Roe average of cells k-1 and k, project the 2r-point stencil of Q and
      * F onto the characteristic fields, split and reconstruct each field,
      * project back. */
     const R gm1 = R(P.gamma - 1);
-    const R* QL = &Qc[(size_t)(k - 1 + 3) * m];
-    const R* QR = &Qc[(size_t)(k + 3) * m];
+    const R* QL = &Qc[(size_t)(k - 1 + r) * m];
+    const R* QR = &Qc[(size_t)(k + r) * m];
     R rl = QL[0], rr = QR[0];
     R ul = QL[1] / rl, ur = QR[1] / rr;
     R vl = m == 4 ? QL[2] / rl : R(0), vr = m == 4 ? QR[2] / rr : R(0);
@@ -495,32 +641,31 @@ static void line_fluxes(const orc_problem& P, const ZA6Const<R>& K, const ReconP
     R c = r_sqrt(c2);
     R Rm[16], Lm[16];
     euler_eigen<R>(m, dir, gm1, u, v, H, c, Rm, Lm);
-    R W[6][4], G[6][4];
-    for (int j = 0; j < 6; ++j) {
-      const R* Qj = &Qc[(size_t)(k - 3 + j + 3) * m];
-      const R* Fj = &Fc[(size_t)(k - 3 + j + 3) * m];
-      for (int s = 0; s < m; ++s) {
-        R w = R(0), g = R(0);
+    R W[2 * R_MAX][4], G[2 * R_MAX][4];
+    for (int j = 0; j < w; ++j) {
+      const R* Qj = &Qc[(size_t)(k - r + j + r) * m];
+      const R* Fj = &Fc[(size_t)(k - r + j + r) * m];
+      for (int s2 = 0; s2 < m; ++s2) {
+        R wv = R(0), g = R(0);
         for (int cc = 0; cc < m; ++cc) {
-          w = w + Lm[s * m + cc] * Qj[cc];
-          g = g + Lm[s * m + cc] * Fj[cc];
+          wv = wv + Lm[s2 * m + cc] * Qj[cc];
+          g = g + Lm[s2 * m + cc] * Fj[cc];
         }
-        W[j][s] = w; G[j][s] = g;
+        W[j][s2] = wv; G[j][s2] = g;
       }
     }
     R gh[4];
-    for (int s = 0; s < m; ++s) {
-      R a = from_state<R>(alpha[s]);
-      R vp[6], vm[6];
-      for (int j = 0; j < 6; ++j) {
-        vp[j] = h * (G[j][s] + a * W[j][s]);
-        vm[5 - j] = h * (G[j][s] - a * W[j][s]);
+    for (int s2 = 0; s2 < m; ++s2) {
+      R a = from_state<R>(alpha[s2]);
+      for (int j = 0; j < w; ++j) {
+        vp[j] = h * (G[j][s2] + a * W[j][s2]);
+        vm[w - 1 - j] = h * (G[j][s2] - a * W[j][s2]);
       }
-      gh[s] = recon_za6<R>(vp, K, RP, nullptr) + recon_za6<R>(vm, K, RP, nullptr);
+      gh[s2] = S(vp, RP) + S(vm, RP);
     }
     for (int cc = 0; cc < m; ++cc) {
       R f = R(0);
-      for (int s = 0; s < m; ++s) f = f + Rm[cc * m + s] * gh[s];
+      for (int s2 = 0; s2 < m; ++s2) f = f + Rm[cc * m + s2] * gh[s2];
       Fhat[(size_t)cc * (n + 1) + k] = to_state(f);
     }
   }
@@ -530,6 +675,7 @@ struct Ctx {
   orc_problem P;
   ReconParams RP;
   int m;
+  int r;          /* order 2r of the scheme */
   double dx, dy;
   size_t ncell;
 };
@@ -540,6 +686,9 @@ static int make_ctx(const orc_problem* p, Ctx* C) {
   if (p->dim != 1 && p->dim != 2) return 1;
   if (p->nx < 1 || p->ny < 1 || (p->dim == 1 && p->ny != 1)) return 1;
   C->m = ncomp(*p);
+  C->r = p->order == 0 ? 3 : p->order;
+  if (C->r < 2 || C->r > R_MAX) return 1;
+  if (C->r != 3 && !g_gen[C->r].set) return 1;   /* tables not handed over */
   C->RP.p = p->p; C->RP.eps = p->eps; C->RP.ai = p->ai; C->RP.mu0 = p->mu0;
   C->RP.linear = p->linear_weights;
   C->dx = (p->xhi - p->xlo) / p->nx;
@@ -555,7 +704,8 @@ static int sweep_fluxes(const Ctx& C, const double* q, int dir, const double* al
   const orc_problem& P = C.P;
   const int m = C.m;
   const int nx = P.nx, ny = P.ny;
-  static const ZA6Const<R> K;
+  const SchemeFor<R> SF(C.r);
+  const Scheme<R>& K = SF.S;
   if (dir == 0) {
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y) {
@@ -763,6 +913,44 @@ int orc_wave_speeds(const orc_problem* p, const double* q, double* alpha /*[2][4
   return bad ? 4 : 0;
 }
 
+/* Tables of the order-2r scheme as n exact rationals num[i]/den[i], in the
+ * layout of oracle/coeffs.py flat_rationals(r).  Returns 0 on success. */
+int orc_set_order_tables(int r, const int64_t* num, const int64_t* den, int n) {
+  if (r < 2 || r > R_MAX || !num || !den) return 1;
+  const int expect = (r + 1) * r + (r + 1) + 2 * r + (r + 1) * (r * (r - 1) / 2) * r + (2 * r - 3);
+  if (n != expect) return 1;
+  GenTab& T = g_gen[r];
+  T.num.assign(num, num + n);
+  T.den.assign(den, den + n);
+  for (int i = 0; i < n; ++i) if (T.den[i] == 0) return 1;
+  T.set = 1;
+  return 0;
+}
+
+/* One reconstruction of the order-2r scheme from v[0..2r-1] in FP64 (fp32 =
+ * 0), FP32 (1) or quad (2, result rounded to FP64); detail (FP64 path only,
+ * may be NULL) receives 3r + 6 values: q_0..q_r, beta_0..beta_{r-1}, beta_d,
+ * beta_r, tau, mu, omega_0..omega_r. */
+double orc_recon_r(int r, const double* v, double p, double eps, int ai, double mu0, int linear,
+                   int prec, double* detail) {
+  if (r < 2 || r > R_MAX || !g_gen[r].set) return NAN;
+  ReconParams RP; RP.p = p; RP.eps = eps; RP.ai = ai; RP.mu0 = mu0; RP.linear = linear;
+  if (prec == 1) {
+    GenConst<float> K(r);
+    float x[2 * R_MAX];
+    for (int j = 0; j < 2 * r; ++j) x[j] = (float)v[j];
+    return (double)recon_gen<float>(x, K, RP, nullptr);
+  }
+  if (prec == 2) {
+    GenConst<quad> K(r);
+    quad x[2 * R_MAX];
+    for (int j = 0; j < 2 * r; ++j) x[j] = (quad)v[j];
+    return (double)recon_gen<quad>(x, K, RP, nullptr);
+  }
+  GenConst<double> K(r);
+  return recon_gen<double>(v, K, RP, detail);
+}
+
 /* Interface fluxes: fx [m][ny][nx+1]; fy [m][ny+1][nx] (2D only, may be NULL). */
 int orc_fluxes(const orc_problem* p, const double* q, double* fx, double* fy) {
   Ctx C; if (make_ctx(p, &C)) return 1;
@@ -787,6 +975,8 @@ int orc_fluxes_lines(const orc_problem* p, const double* q, int dir, const int* 
   int bad = wave_speeds(P, q, dir, a, &s);
   const int n = dir == 0 ? P.nx : P.ny;
   const int m = C.m;
+  const SchemeFor<float> SF32(C.r);
+  const SchemeFor<double> SF64(C.r);
 #pragma omp parallel for schedule(dynamic)
   for (int l = 0; l < nl; ++l) {
     const double* lp[4];
@@ -795,11 +985,9 @@ int orc_fluxes_lines(const orc_problem* p, const double* q, int dir, const int* 
     const size_t stride = dir == 0 ? 1 : (size_t)P.nx;
     double* o = out + (size_t)l * m * (n + 1);
     if (P.recon_fp32) {
-      static const ZA6Const<float> K;
-      line_fluxes<float>(P, K, C.RP, dir, a, n, dir == 0 ? P.bc_x : P.bc_y, lp, stride, o);
+      line_fluxes<float>(P, SF32.S, C.RP, dir, a, n, dir == 0 ? P.bc_x : P.bc_y, lp, stride, o);
     } else {
-      static const ZA6Const<double> K;
-      line_fluxes<double>(P, K, C.RP, dir, a, n, dir == 0 ? P.bc_x : P.bc_y, lp, stride, o);
+      line_fluxes<double>(P, SF64.S, C.RP, dir, a, n, dir == 0 ? P.bc_x : P.bc_y, lp, stride, o);
     }
   }
   return bad ? 4 : 0;

@@ -43,6 +43,7 @@ class Problem:
     mu0: float = 1e-40
     lf: int = LF_PER_FIELD
     linear_weights: int = 0
+    order: int = 3          # r of the order-2r central-upwind scheme (3: WENO-ZA6)
 
     @property
     def m(self) -> int:
