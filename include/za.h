@@ -70,7 +70,7 @@ typedef struct {
   int32_t system;          /* za_system                                      */
   int32_t nx, ny;          /* cells; ny = 1 when dim == 1                    */
   double  xlo, xhi, ylo, yhi;
-  int32_t bc_x, bc_y;      /* za_bc; three ghost cells per side             */
+  int32_t bc_x, bc_y;      /* za_bc; r ghost cells per side                  */
   double  gamma;           /* ratio of specific heats (1.4 in the paper)     */
   double  adv_speed[2];    /* advection velocity (ZA_ADVECTION)              */
   double  cfl;             /* CFL number (0.45 in the paper)                 */
@@ -82,6 +82,11 @@ typedef struct {
   double  mu0;             /* mu_0 of eq:aimu (1e-40 FP64, 1e-8 FP32)        */
   int32_t lf;              /* za_lf                                          */
   int32_t linear_weights;  /* 1: omega = d (the linear central flux), tests  */
+  int32_t order;           /* r of the order-2r central-upwind scheme: 3 (or  */
+                           /* 0) WENO-ZA6, Section 3; 2, 4, 5 the fourth-,    */
+                           /* eighth- and tenth-order schemes of Appendix A,  */
+                           /* FP64 only (ZA_ERR_UNSUPPORTED otherwise; the    */
+                           /* server takes r = 3 only)                        */
 } za_problem;
 
 typedef struct za_ctx za_ctx;

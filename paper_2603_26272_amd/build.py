@@ -16,7 +16,7 @@ INC = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libza.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["za_lib.hip", "za_server.hip"]
+SOURCES = ["za_lib.hip", "za_server.hip", "za_order.hip"]
 ARCH = os.environ.get("ZA_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INC, "-I", CSRC,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]

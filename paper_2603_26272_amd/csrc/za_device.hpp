@@ -10,6 +10,8 @@
 // the state is always double.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include "za_order_tables.hpp"
 #include <stdint.h>
 
 namespace za {
@@ -21,7 +23,9 @@ namespace za {
 template <class T>
 struct WeightCfg {
   T eps16;    // 16 epsilon   (Z weights, indicators of 2v scaled by 4)
-  T eps4;     // 4 epsilon    (Ai weights after dividing by mu(2v)^2)
+  T eps4;     // 4 epsilon    (Ai weights after dividing by mu(2v)^2;
+              //               order-2r Z weights on 2v)
+  T eps1;     // epsilon      (order-2r Ai weights after dividing by mu(2v)^2)
   T mu0x2;    // 2 mu_0       (descaler of 2v)
   T p;        // power parameter (1 on the fast path)
   int ai;     // 1: affine-invariant descaler
@@ -173,20 +177,109 @@ __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const Weigh
   return div_nr(fma(a0, q0, fma(a1, q1, fma(a2, q2, a3 * q3))), (a0 + a1) + (a2 + a3));
 }
 
+// ---------------------------------------------------------------------------
+// Order-2r central-upwind reconstruction for r != 3 (Section 2, Section 3 and
+// Appendix A), from s = (s_0..s_{2r-1}) = 2 (f_{i-r+1}, .., f_{i+r}); returns
+// twice the reconstructed flux, like za6.  Candidates on S_k (k = 0..r, S_r
+// downwind), indicators as sums of squares of first differences (the printed
+// quadratic forms, factored; see za_order_tables.hpp), the downwind weight's
+// indicator the mean of the r upwind ones and beta_d, tau from the
+// (2r-1)-th difference, Z weights (or linear / Ai / p != 1 under
+// WV_GENERAL) in the direct form.  beta(2f) = 4 beta(f) and tau(2f) =
+// 4 tau(f), so the epsilon is 4 eps (Ai: eps, after dividing by mu(2f)^2).
+// ---------------------------------------------------------------------------
+template <class T, int R, int WV>
+__device__ __forceinline__ T zar(const T (&s)[2 * R], const WeightCfg<T>& w) {
+  typedef OrderTables<R> Tb;
+  constexpr int S = 2 * R;
+  T g[S - 1];
+#pragma unroll
+  for (int j = 0; j < S - 1; ++j) g[j] = s[j + 1] - s[j];
+  T q[R + 1];
+#pragma unroll
+  for (int k = 0; k <= R; ++k) {
+    T acc = T(Tb::ck(k, 0)) * s[k];
+#pragma unroll
+    for (int j = 1; j < R; ++j) acc = fma(T(Tb::ck(k, j)), s[k + j], acc);
+    q[k] = acc;
+  }
+  if (WV == WV_GENERAL && w.linear) {
+    T acc = T(Tb::d(0)) * q[0];
+#pragma unroll
+    for (int k = 1; k <= R; ++k) acc = fma(T(Tb::d(k)), q[k], acc);
+    return acc;
+  }
+  T beta[R + 1];
+#pragma unroll
+  for (int k = 0; k <= R; ++k) {
+    T b = T(0);
+#pragma unroll
+    for (int l = 0; l < R - 1; ++l) {
+      T t = g[k + l];
+#pragma unroll
+      for (int m = l + 1; m < R - 1; ++m) t = fma(T(Tb::U(k, l, m)), g[k + m], t);
+      b = fma(T(Tb::lam(k, l)) * t, t, b);
+    }
+    beta[k] = b;
+  }
+  // beta[R] holds beta_d; the downwind candidate takes the mean
+  T sum = beta[0];
+#pragma unroll
+  for (int k = 1; k <= R; ++k) sum += beta[k];
+  beta[R] = sum * T(1.0 / (R + 1));
+  T t5 = T(Tb::ctau(0)) * s[0];
+#pragma unroll
+  for (int j = 1; j < S; ++j) t5 = fma(T(Tb::ctau(j)), s[j], t5);
+  T tau = t5 * t5;
+  T eps = w.eps4;
+  if (WV == WV_GENERAL && w.ai) {
+    T mean = s[0];
+#pragma unroll
+    for (int j = 1; j < S; ++j) mean += s[j];
+    mean *= T(1.0 / S);
+    T mu = fabs(s[0] - mean);
+#pragma unroll
+    for (int j = 1; j < S; ++j) mu += fabs(s[j] - mean);
+    mu = fma(mu, T(1.0 / S), w.mu0x2);
+    const T imu2 = rcp_nr(mu * mu);
+#pragma unroll
+    for (int k = 0; k <= R; ++k) beta[k] *= imu2;
+    tau *= imu2;
+    eps = w.eps1;
+  }
+  T num = T(0), den = T(0);
+#pragma unroll
+  for (int k = 0; k <= R; ++k) {
+    T gk = tau * rcp_nr(beta[k] + eps);
+    if (WV == WV_GENERAL && w.p != T(1)) gk = pow(gk, w.p);
+    const T a = T(Tb::d(k)) * (T(1) + gk);
+    num = fma(a, q[k], num);
+    den += a;
+  }
+  return div_nr(num, den);
+}
+
 // Both Lax-Friedrichs halves of one characteristic field at one interface
 // (eq:LF): with s^{+-}_j = g_j +- a w_j = 2 f^{+-}_j,
-// F = (R(s^+_{i-2..i+3}) + R(s^-_{i+3..i-2})) / 2 where R returns twice the
-// reconstruction.
-template <class T, int WV>
-__device__ __forceinline__ T split_pair(const T (&w)[6], const T (&g)[6], T a, const WeightCfg<T>& cfg) {
-  T p[6], m[6];
+// F = (R(s^+_{i-r+1..i+r}) + R(s^-_{i+r..i-r+1})) / 2 where R returns twice
+// the reconstruction.
+template <class T, int WV, int R = 3>
+__device__ __forceinline__ T split_pair(const T (&w)[2 * R], const T (&g)[2 * R], T a, const WeightCfg<T>& cfg) {
+  T p[2 * R], m[2 * R];
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
+  for (int j = 0; j < 2 * R; ++j) {
     p[j] = fma(a, w[j], g[j]);
     m[j] = fma(-a, w[j], g[j]);
   }
-  return T(0.5) * (za6<T, WV>(p[0], p[1], p[2], p[3], p[4], p[5], cfg) +
-                   za6<T, WV>(m[5], m[4], m[3], m[2], m[1], m[0], cfg));
+  if constexpr (R == 3) {
+    return T(0.5) * (za6<T, WV>(p[0], p[1], p[2], p[3], p[4], p[5], cfg) +
+                     za6<T, WV>(m[5], m[4], m[3], m[2], m[1], m[0], cfg));
+  } else {
+    T mr[2 * R];
+#pragma unroll
+    for (int j = 0; j < 2 * R; ++j) mr[j] = m[2 * R - 1 - j];
+    return T(0.5) * (zar<T, R, WV>(p, cfg) + zar<T, R, WV>(mr, cfg));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -259,8 +352,8 @@ __device__ __forceinline__ void roe_side(const T* __restrict__ rec, int fs, int 
 }
 
 // ---------------------------------------------------------------------------
-// Characteristic-wise WENO-ZA6 flux of the Euler equations at one interface
-// in the sweep-normal frame, from the records of its six-point stencil
+// Characteristic-wise WENO-ZA6 (order 2R) flux of the Euler equations at one
+// interface in the sweep-normal frame, from the records of its 2R-point stencil
 // (value of field f at stencil point j: rec[f * fs + off[j]]).  The y-sweep
 // builds its records in the permuted frame and permutes the result back; the
 // two tangential fields share one eigenvalue and one LF speed, so their order
@@ -274,18 +367,18 @@ __device__ __forceinline__ void roe_side(const T* __restrict__ rec, int fs, int 
 //   B = (u Q0 - Q1)/(2c), K = u Q1 + v Q2 - E, b1 = (gamma-1)/c^2,
 //   b2 = b1 q2  (the textbook left eigenvectors, factored).
 // ---------------------------------------------------------------------------
-template <class T, int M, int WV>
-__device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, const int (&off)[6], T gm1,
+template <class T, int M, int WV, int R = 3>
+__device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, const int (&off)[2 * R], T gm1,
                                            const T (&alpha)[M], const WeightCfg<T>& cfg, T (&Fh)[M]) {
   typedef RecLayout<M> Lo;
 #define ZA_R(f, j) rec[(f) * fs + off[j]]
-  // Roe average of cells 2 (= i) and 3 (= i+1)
-  const T sl = ZA_R(Lo::SR, 2), sr = ZA_R(Lo::SR, 3);
+  // Roe average of the cells R-1 (= i) and R (= i+1) of the stencil
+  const T sl = ZA_R(Lo::SR, R - 1), sr = ZA_R(Lo::SR, R);
   const T iw = rcp_nr(sl + sr);
   const T wl = sl * iw, wr = sr * iw;
   T unl, utl, Hl, unr, utr, Hr;
-  roe_side<T, M>(rec, fs, off[2], gm1, unl, utl, Hl);
-  roe_side<T, M>(rec, fs, off[3], gm1, unr, utr, Hr);
+  roe_side<T, M>(rec, fs, off[R - 1], gm1, unl, utl, Hl);
+  roe_side<T, M>(rec, fs, off[R], gm1, unr, utr, Hr);
   const T u = fma(wl, unl, wr * unr);
   const T v = M == 4 ? fma(wl, utl, wr * utr) : T(0);
   const T H = fma(wl, Hl, wr * Hr);
@@ -297,9 +390,9 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
   const T hb1 = T(0.5) * b1, hb2 = hb1 * q2;
   const T hic = T(0.5) * ic;
   // project the stencil onto the characteristic fields
-  T W[M][6], G[M][6];
+  T W[M][2 * R], G[M][2 * R];
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
+  for (int j = 0; j < 2 * R; ++j) {
     const T Q0 = ZA_R(Lo::Q0, j), Q1 = ZA_R(Lo::Q1, j), E = ZA_R(Lo::E, j);
     const T Q2 = M == 4 ? ZA_R(M == 4 ? Lo::Q2 : 0, j) : T(0);
     const T F1 = ZA_R(Lo::F1, j), F3 = ZA_R(Lo::F3, j);
@@ -329,7 +422,7 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
 #undef ZA_R
   T gh[M];
 #pragma unroll
-  for (int s = 0; s < M; ++s) gh[s] = split_pair<T, WV>(W[s], G[s], alpha[s], cfg);
+  for (int s = 0; s < M; ++s) gh[s] = split_pair<T, WV, R>(W[s], G[s], alpha[s], cfg);
   // back-projection F = R g
   const T s03 = gh[0] + gh[M - 1], d30 = gh[M - 1] - gh[0];
   const T sum = s03 + gh[1];

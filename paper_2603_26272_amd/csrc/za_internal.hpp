@@ -38,3 +38,25 @@ struct za_ctx {
 };
 
 za_status za_validate(const za_problem* p, std::string* why);
+
+// r of the order-2r scheme (0 selects WENO-ZA6, r = 3)
+inline int order_of(const za_problem& p) { return p.order == 0 ? 3 : p.order; }
+
+template <class T>
+inline za::CfgArg<T> make_cfg(const za_problem& p) {
+  za::CfgArg<T> c;
+  // exact power-of-two rescalings of the reconstruction (see za6() and zar())
+  c.w.eps16 = (T)(16.0 * p.eps);
+  c.w.eps4 = (T)(4.0 * p.eps);
+  c.w.eps1 = (T)p.eps;
+  c.w.mu0x2 = (T)(2.0 * p.mu0);
+  c.w.p = (T)p.p;
+  c.w.ai = p.affine_invariant;
+  c.w.linear = p.linear_weights;
+  return c;
+}
+
+// Sweeps of the order-2r schemes with r != 3 (za_order.hip): FP64, general
+// weights, every mode; `a` as for the r = 3 kernels.
+void launch_x_order(za_ctx* c, int mode, const za::SweepArgs& a);
+void launch_y_order(za_ctx* c, int mode, const za::SweepArgs& a);

@@ -206,8 +206,8 @@ __device__ __forceinline__ void stage_cell(const double* __restrict__ base, size
 
 // Interface flux from the records of its six-point stencil; the result is
 // returned in the state's own component order.
-template <int SYS, int M, int DIR, class T, int WV>
-__device__ __forceinline__ void stencil_flux(const T* __restrict__ rec, int fs, const int (&off)[6],
+template <int SYS, int M, int DIR, class T, int WV, int R = 3>
+__device__ __forceinline__ void stencil_flux(const T* __restrict__ rec, int fs, const int (&off)[2 * R],
                                              const Phys& ph, const DevCtl* ctl, const WeightCfg<T>& cfg,
                                              T (&Fh)[M]) {
   if (SYS == SYS_EULER) {
@@ -220,7 +220,7 @@ __device__ __forceinline__ void stencil_flux(const T* __restrict__ rec, int fs, 
       al[0] = (T)ctl->alpha[0][0]; al[1] = (T)ctl->alpha[0][1]; al[MM - 1] = (T)ctl->alpha[0][3];
     }
     T F[MM];
-    euler_flux<T, MM, WV>(rec, fs, off, (T)ph.gm1, al, cfg, F);
+    euler_flux<T, MM, WV, R>(rec, fs, off, (T)ph.gm1, al, cfg, F);
     if (MM == 4 && DIR == 1) {
       Fh[0] = F[0]; Fh[1 % M] = F[2 % MM]; Fh[2 % M] = F[1]; Fh[3 % M] = F[3 % MM];
     } else {
@@ -228,13 +228,13 @@ __device__ __forceinline__ void stencil_flux(const T* __restrict__ rec, int fs, 
       for (int c = 0; c < M; ++c) Fh[c] = F[c];
     }
   } else {
-    T w[6], g[6];
+    T w[2 * R], g[2 * R];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
+    for (int j = 0; j < 2 * R; ++j) {
       w[j] = rec[off[j]];
       g[j] = rec[fs + off[j]];
     }
-    Fh[0] = split_pair<T, WV>(w, g, (T)ctl->alpha[DIR][0], cfg);
+    Fh[0] = split_pair<T, WV, R>(w, g, (T)ctl->alpha[DIR][0], cfg);
   }
 }
 
@@ -257,10 +257,11 @@ struct CfgArg { WeightCfg<T> w; };
 
 // ---------------------------------------------------------------------------
 // x-sweep: one wavefront per line segment of 64 interfaces / 63 cells.  The
-// wavefront first builds the records of its 69 cells (63 + the 6-cell halo,
-// coalesced loads) in LDS; each lane then computes one interface flux from
-// six consecutive records, and the fluxes meet in LDS again for the
-// conservative difference.  Used for the 2D x-direction and for 1D problems.
+// wavefront first builds the records of its 63 + 2R cells (the cells and the
+// stencil halo, coalesced loads; R = 3: 69) in LDS; each lane then computes
+// one interface flux from 2R consecutive records, and the fluxes meet in LDS
+// again for the conservative difference.  Used for the 2D x-direction and
+// for 1D problems.
 // ---------------------------------------------------------------------------
 constexpr int XS_CELLS = 63;
 #ifndef ZA_XS_WAVES
@@ -269,10 +270,12 @@ constexpr int XS_CELLS = 63;
 #ifndef ZA_YS_WAVES
 #define ZA_YS_WAVES 3
 #endif
-constexpr int XS_REC = 72;    // record slots per field and wavefront (69 used)
+// record slots per field and wavefront: the 63 cells and a 2R-cell halo
+__host__ __device__ constexpr int xs_rec(int R) { return (XS_CELLS + 2 * R + 7) / 8 * 8; }
 
-template <int SYS, int M, class T, int MODE, int WV>
+template <int SYS, int M, class T, int MODE, int WV, int R = 3>
 __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>& cfg, int bid) {
+  constexpr int XS_REC = xs_rec(R);
   if (a.check_active && !a.ctl->active) return;
   constexpr int NF = NumFields<SYS, M>::value;
   __shared__ T xr[4][NF * XS_REC];
@@ -288,16 +291,18 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
   const size_t cs = (size_t)nx * ny;
   const size_t row = (size_t)line * nx;
   if (live) {
-    for (int idx = lane; idx < XS_CELLS + 6; idx += 64) {
-      const int j = bc_map(c0 - 3 + idx, nx, a.g.bc_x);
+    for (int idx = lane; idx < XS_CELLS + 2 * R; idx += 64) {
+      const int j = bc_map(c0 - R + idx, nx, a.g.bc_x);
       stage_cell<SYS, M, 0, T>(a.q + row, cs, (size_t)j, a.ph, &xr[wv][idx], XS_REC);
     }
   }
   wave_sync();   // the records and fluxes of a wavefront are its own
   if (live && k <= nx) {
     T F[M];
-    const int off[6] = {lane, lane + 1, lane + 2, lane + 3, lane + 4, lane + 5};
-    stencil_flux<SYS, M, 0, T, WV>(&xr[wv][0], XS_REC, off, a.ph, a.ctl, cfg.w, F);
+    int off[2 * R];
+#pragma unroll
+    for (int j = 0; j < 2 * R; ++j) off[j] = lane + j;
+    stencil_flux<SYS, M, 0, T, WV, R>(&xr[wv][0], XS_REC, off, a.ph, a.ctl, cfg.w, F);
     if (MODE == MODE_FLUX) {
       if (lane < XS_CELLS || k == nx) {
 #pragma unroll
@@ -324,9 +329,9 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
         if (sizeof(T) == sizeof(double) && SYS == SYS_EULER) {
           typedef RecLayout<(M == 1 ? 4 : M)> Lo;
           const int f = c == 0 ? (int)Lo::Q0 : (c == M - 1 ? (int)Lo::E : (c == 1 ? (int)Lo::Q1 : (int)Lo::Q2));
-          qc[c] = (double)xr[wv][f * XS_REC + lane + 3];
+          qc[c] = (double)xr[wv][f * XS_REC + lane + R];
         } else if (sizeof(T) == sizeof(double)) {
-          qc[c] = (double)xr[wv][lane + 3];
+          qc[c] = (double)xr[wv][lane + R];
         } else {
           qc[c] = a.q[c * cs + idx];
         }
@@ -379,8 +384,9 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
 constexpr int YS_TILE_MIN = 16;
 constexpr int YS_COLS = 16;
 constexpr int YS_ROWS = 64 / YS_COLS;
-constexpr int YS_RING = YS_ROWS + 5;
 constexpr int YS_FSLOT = YS_ROWS + 1;
+// record rows of one step's stencils (R = 3: 9)
+__host__ __device__ constexpr int ys_ring(int R) { return YS_ROWS + 2 * R - 1; }
 
 // Issue priority of a wavefront that has done step st of nst: it falls as the
 // wavefront advances, so each SIMD favours the wavefronts that are behind and
@@ -398,9 +404,10 @@ __device__ __forceinline__ void progress_prio(int st, int nst) {
 // One wavefront's tile: columns x0 .. x0+YS_COLS-1, cell rows [y0, ylast)
 // (interfaces y0 .. ylast).  MODE_STAGE folds the wave speeds of the new
 // states into rs.
-template <int SYS, int M, class T, int MODE, int WV>
+template <int SYS, int M, class T, int MODE, int WV, int R = 3>
 __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>& cfg, int x0, int y0, int ylast,
                                              double (&rs)[NPART]) {
+  constexpr int YS_RING = ys_ring(R);
   constexpr int NF = NumFields<SYS, M>::value;
   constexpr int RS = NF * YS_COLS + 32 / (int)sizeof(T);   // ring row stride, padded by 32 bytes
   __shared__ T ring[4][YS_RING * RS];
@@ -415,12 +422,12 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
   const double* col = a.q + (xin ? x : 0);
   T* const rw = &ring[wv][cl];
   double(*const fw)[M][YS_COLS] = fb[wv];
-  auto slot = [&](int r) { return (r - y0 + 3) % YS_RING; };     // r >= y0 - 3
+  auto slot = [&](int r) { return (r - y0 + R) % YS_RING; };     // r >= y0 - R
   auto fslot = [&](int k) { return (k - y0 + 1) % YS_FSLOT; };   // k >= y0 - 1
-  // rows y0-3 .. y0+YS_ROWS+1 for the first step
+  // rows y0-R .. y0+YS_ROWS+R-2 for the first step
   for (int i = g; i < YS_RING; i += YS_ROWS) {
     if (xin) {
-      const int r = y0 - 3 + i;
+      const int r = y0 - R + i;
       stage_cell<SYS, M, 1, T>(col, cs, (size_t)bc_map(r, ny, a.g.bc_y) * nx, a.ph, rw + slot(r) * RS, YS_COLS);
     }
   }
@@ -432,8 +439,8 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
     const int k = k0 + g;
     const bool act = k <= kend && xin;
     // the cell row this lane adds for the next step's stencils
-    const int rn = k0 + YS_ROWS + 2 + g;
-    const bool need = rn <= kend + 2 && xin;
+    const int rn = k0 + YS_ROWS + R - 1 + g;
+    const bool need = rn <= kend + R - 1 && xin;
     double qp[M];
     if (need) {
       const size_t off = (size_t)bc_map(rn, ny, a.g.bc_y) * nx;
@@ -442,10 +449,10 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
     }
     if (act) {
       T F[M];
-      int off[6];
+      int off[2 * R];
 #pragma unroll
-      for (int j = 0; j < 6; ++j) off[j] = slot(k - 3 + j) * RS;
-      stencil_flux<SYS, M, 1, T, WV>(rw, YS_COLS, off, a.ph, a.ctl, cfg.w, F);
+      for (int j = 0; j < 2 * R; ++j) off[j] = slot(k - R + j) * RS;
+      stencil_flux<SYS, M, 1, T, WV, R>(rw, YS_COLS, off, a.ph, a.ctl, cfg.w, F);
 #pragma unroll
       for (int c = 0; c < M; ++c) fw[fslot(k)][c][cl] = (double)F[c];
       if (MODE == MODE_FLUX && (k < kend || k == ny)) {
@@ -472,7 +479,7 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
       if (MODE == MODE_STAGE) cell_speeds<SYS, M>(qnew, a.ph, rs);
     }
     if (need) {
-      // row rn takes the slot of row rn - YS_RING = k0 - 3 + g, which only
+      // row rn takes the slot of row rn - YS_RING = k0 - R + g, which only
       // this step's stencils (above the synchronisation) read
       T* rec = rw + slot(rn) * RS;
       if (SYS == SYS_EULER) {
@@ -495,7 +502,7 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
 
 // Block (bx, by) owns 64 columns, one YS_COLS-column tile per wavefront, and
 // band by of the ceil(ny / ytile) bands of (near) equal height.
-template <int SYS, int M, class T, int MODE, int WV>
+template <int SYS, int M, class T, int MODE, int WV, int R = 3>
 __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>& cfg, int bx, int by, int gx) {
   if (a.check_active && !a.ctl->active) return;
   double rs[NPART];
@@ -504,7 +511,7 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
   const int ny = a.g.ny;
   const int nb = (ny + a.ytile - 1) / a.ytile;
   const int y0 = (int)((long long)by * ny / nb), ylast = (int)((long long)(by + 1) * ny / nb);
-  sweep_y_tile<SYS, M, T, MODE, WV>(a, cfg, bx * 64 + wave_id() * YS_COLS, y0, ylast, rs);
+  sweep_y_tile<SYS, M, T, MODE, WV, R>(a, cfg, bx * 64 + wave_id() * YS_COLS, y0, ylast, rs);
   if (MODE == MODE_STAGE && a.part)
     block_max_store(rs, a.part + ((size_t)by * gx + bx) * NPART);
 }
@@ -516,17 +523,17 @@ template <int SYS, int M, class T, int MODE, int WV>
 __global__ __launch_bounds__(256, ZA_XS_WAVES) void k_sweep_x(SweepArgs a, CfgArg<T> cfg) {
   sweep_x_body<SYS, M, T, MODE, WV>(a, cfg, blockIdx.x);
 }
-template <int SYS, int M, class T, int MODE, int WV>
+template <int SYS, int M, class T, int MODE, int WV, int R = 3>
 __global__ __launch_bounds__(256) void k_sweep_x_any(SweepArgs a, CfgArg<T> cfg) {
-  sweep_x_body<SYS, M, T, MODE, WV>(a, cfg, blockIdx.x);
+  sweep_x_body<SYS, M, T, MODE, WV, R>(a, cfg, blockIdx.x);
 }
 template <int SYS, int M, class T, int MODE, int WV>
 __global__ __launch_bounds__(256, ZA_YS_WAVES) void k_sweep_y(SweepArgs a, CfgArg<T> cfg) {
   sweep_y_body<SYS, M, T, MODE, WV>(a, cfg, blockIdx.x, blockIdx.y, gridDim.x);
 }
-template <int SYS, int M, class T, int MODE, int WV>
+template <int SYS, int M, class T, int MODE, int WV, int R = 3>
 __global__ __launch_bounds__(256) void k_sweep_y_any(SweepArgs a, CfgArg<T> cfg) {
-  sweep_y_body<SYS, M, T, MODE, WV>(a, cfg, blockIdx.x, blockIdx.y, gridDim.x);
+  sweep_y_body<SYS, M, T, MODE, WV, R>(a, cfg, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 

@@ -55,6 +55,11 @@ za_status za_validate(const za_problem* p, std::string* why) {
   if (p->affine_invariant && !(p->mu0 > 0.0)) return fail("mu0 must be positive");
   if (p->precision == ZA_FP32_RECON && (p->eps < 1e-37 || (p->affine_invariant && p->mu0 < 1e-18)))
     return fail("FP32 reconstruction needs eps >= 1e-37 and mu0 >= 1e-18 (normal FP32 range)");
+  if (p->order != 0 && (p->order < 2 || p->order > 5)) return fail("order r must be 2, 3, 4 or 5");
+  if (order_of(*p) != 3 && p->precision != ZA_FP64) {
+    if (why) *why = "orders other than r = 3 run in FP64 only";
+    return ZA_ERR_UNSUPPORTED;
+  }
   return ZA_OK;
 }
 
@@ -98,18 +103,6 @@ static za_status hip_fail(za_ctx* c, hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail((c), e_, (what));   \
   } while (0)
 
-template <class T>
-static CfgArg<T> make_cfg(const za_problem& p) {
-  CfgArg<T> c;
-  // exact power-of-two rescalings of the reconstruction (see za6())
-  c.w.eps16 = (T)(16.0 * p.eps);
-  c.w.eps4 = (T)(4.0 * p.eps);
-  c.w.mu0x2 = (T)(2.0 * p.mu0);
-  c.w.p = (T)p.p;
-  c.w.ai = p.affine_invariant;
-  c.w.linear = p.linear_weights;
-  return c;
-}
 
 static void timed_begin(za_ctx* c, int cls) {
   if (!c->timing) return;
@@ -196,6 +189,11 @@ static void launch_y_sys(za_ctx* c, int mode, const SweepArgs& a) {
 
 static void launch_x(za_ctx* c, int mode, const SweepArgs& a) {
   timed_begin(c, 0);
+  if (order_of(c->prob) != 3) {
+    launch_x_order(c, mode, a);
+    timed_end(c, 0);
+    return;
+  }
   switch (c->prob.system) {
     case ZA_EULER:
       if (c->prob.dim == 1) launch_x_sys<SYS_EULER, 3>(c, mode, a); else launch_x_sys<SYS_EULER, 4>(c, mode, a);
@@ -209,6 +207,11 @@ static void launch_x(za_ctx* c, int mode, const SweepArgs& a) {
 
 static void launch_y(za_ctx* c, int mode, const SweepArgs& a) {
   timed_begin(c, 1);
+  if (order_of(c->prob) != 3) {
+    launch_y_order(c, mode, a);
+    timed_end(c, 1);
+    return;
+  }
   switch (c->prob.system) {
     case ZA_EULER: launch_y_sys<SYS_EULER, 4>(c, mode, a); break;
     case ZA_ADVECTION: launch_y_sys<SYS_ADV, 1>(c, mode, a); break;

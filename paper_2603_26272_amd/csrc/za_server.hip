@@ -493,7 +493,8 @@ za_status za_server_submit(za_server* sv, const za_problem* p, const double* q0,
   std::string why;
   if (za_validate(p, &why) != ZA_OK) return ZA_ERR_ARG;
   // batches run the paper's weights (Z type, p = 1, mu = 1) on the Euler equations
-  if (p->system != ZA_EULER || p->p != 1.0 || p->affine_invariant || p->linear_weights) return ZA_ERR_UNSUPPORTED;
+  if (p->system != ZA_EULER || p->p != 1.0 || p->affine_invariant || p->linear_weights || order_of(*p) != 3)
+    return ZA_ERR_UNSUPPORTED;
   int sb, xb, ys, yb;
   if (footprint(*p, &sb, &xb, &ys, &yb) > sv->budget) return ZA_ERR_NOMEM;
   auto r = std::make_unique<Req>();

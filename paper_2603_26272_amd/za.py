@@ -43,6 +43,7 @@ class ZaProblem(C.Structure):
         ("mu0", C.c_double),
         ("lf", C.c_int32),
         ("linear_weights", C.c_int32),
+        ("order", C.c_int32),
     ]
 
     @classmethod

@@ -37,3 +37,39 @@ def test_host_only_calls():
     assert za.workspace_bytes(P) >= 3 * 4 * 100 * 50 * 8
     assert za.state_count(Problem(dim=3)) == 0
     assert za.status_str(0) == "ok" and za.status_str(4).startswith("non-finite")
+
+
+def test_order_validation_host_side():
+    from paper_2603_26272_amd import za
+    from paper_2603_26272_amd.problem import Problem
+    for r in (0, 2, 3, 4, 5):
+        assert za.state_count(Problem(dim=1, nx=40, order=r)) == 3 * 40
+    for r in (1, 6, -2):
+        assert za.state_count(Problem(dim=1, nx=40, order=r)) == 0
+    assert za.state_count(Problem(dim=1, nx=40, order=4).fp32()) == 0   # FP64 only
+    assert za.state_count(Problem(dim=1, nx=40, order=3).fp32()) == 3 * 40
+
+
+def test_problem_struct_layout_matches_header(tmp_path):
+    """The binding's ctypes mirror of za_problem has the C layout (size and
+    every field offset), checked with the host C compiler."""
+    import ctypes
+    import shutil
+    import subprocess
+    from paper_2603_26272_amd import za
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        import pytest
+        pytest.skip("no host C compiler")
+    fields = [n for n, _ in za.ZaProblem._fields_]
+    src = tmp_path / "layout.c"
+    inc = os.path.join(ROOT, "include")
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"za.h\"\nint main(void){\n"
+                   "printf(\"%zu\\n\", sizeof(za_problem));\n" +
+                   "".join(f"printf(\"%zu\\n\", offsetof(za_problem, {f}));\n" for f in fields) +
+                   "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-I", inc, str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got[0] == ctypes.sizeof(za.ZaProblem)
+    assert got[1:] == [getattr(za.ZaProblem, f).offset for f in fields]
