@@ -34,6 +34,10 @@ FLOPS_2D = {
     "y": {"interface": 1371.0, "cell_flux": 15.0, "cell_update": 32},
 }
 FLOPS_1D_IR = 1000.0 + 10.0   # 1D Euler: per interface + per-cell physical flux
+# 2D Euler FLOPs per interface of the order-2r schemes, same count (the
+# oracle evaluates the indicators of r != 3 as the defining integral of
+# eq:SI, which is not a minimal count; see the order study).
+FLOPS_2D_ORDER_IR = {2: 751.0, 3: 1371.0, 4: 3559.0, 5: 7843.0}
 PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 FLOP/clk
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (packed issue)
 PEAK_HBM_GBS = 8000.0
@@ -311,6 +315,46 @@ def study_c3(torch, Context, n=4096, steps=200):
     return out
 
 
+def study_orders(torch, Context, n=2048, steps=20):
+    """The fourth- to tenth-order schemes (r = 2..5) on the 2D Euler workload
+    (FP64, 2048^2, 20 steps each, per-kernel HIP-event times), and the
+    convergence order of the 2D Euler right-hand side on the smooth density
+    wave (n = 16, 32, 64) against its exact value."""
+    import math
+
+    import numpy as np
+
+    from paper_2603_26272_amd import workloads as W
+    out = {"study": "even orders 2r = 4, 6, 8, 10 (2D Euler FP64)", "runs": [], "rhs_convergence": []}
+    P, q0 = W.quadrants_2d(0, n)
+    ir_step = 3 * ir_per_rhs(n, n)
+    for r in (2, 3, 4, 5):
+        Pr = P.with_(order=r)
+        _, wall, info, avg_ms, counts = run_gpu(Pr, q0, steps, 2, torch, Context)
+        fl = {d: ((n + 1) * n if d == "x" else n * (n + 1)) * FLOPS_2D_ORDER_IR[r] for d in ("x", "y")}
+        out["runs"].append({
+            "r": r, "order": 2 * r, "steps": steps, "IR_s": ir_step * steps / wall,
+            "ms_per_step": wall / steps * 1e3, "x_ms": avg_ms[0], "y_ms": avg_ms[1],
+            "oracle_flop_per_ir": FLOPS_2D_ORDER_IR[r],
+            "x_tflops_oracle_count": fl["x"] / (avg_ms[0] * 1e-3) / 1e12,
+            "y_tflops_oracle_count": fl["y"] / (avg_ms[1] * 1e-3) / 1e12})
+    for r in (2, 3, 4, 5):
+        row = {"r": r, "linf": []}
+        for m in (16, 32, 64):
+            Pw, qw = W.smooth_wave_2d(m)
+            Pw = Pw.with_(order=r)
+            q = torch.from_numpy(qw).to("cuda")
+            with Context(Pw) as ctx:
+                L = ctx.rhs(q).cpu().numpy()
+            x = W.centres(m, 0.0, 1.0)[None, :]
+            y = W.centres(m, 0.0, 1.0)[:, None]
+            exact = -0.8 * math.pi * np.cos(2.0 * math.pi * (x + y))   # -(rho_x + rho_y)
+            row["linf"].append(float(np.abs(L[0] - exact).max()))
+        row["rates"] = [math.log2(a / b) for a, b in zip(row["linf"], row["linf"][1:])]
+        out["rhs_convergence"].append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,7 +370,7 @@ def main():
                     help="Poisson rates (req/s) of the serving leg; the full sweep is 10,25,50,100,200")
     ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--serving-budget-gb", type=float, default=4.0)
-    ap.add_argument("--study", choices=["c0", "c1", "c3", "serving"], default=None,
+    ap.add_argument("--study", choices=["c0", "c1", "c3", "orders", "serving"], default=None,
                     help="run one workload study instead of the benchmark line")
     args = ap.parse_args()
 
@@ -349,6 +393,8 @@ def main():
             res = study_c1(torch, Context)
         elif args.study == "c3":
             res = study_c3(torch, Context)
+        elif args.study == "orders":
+            res = study_orders(torch, Context)
         else:
             rates = [float(x) for x in args.serving_rates.split(",") if x]
             res = {"study": "serving sweep", "hbm_budget_gb": args.serving_budget_gb,

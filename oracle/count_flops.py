@@ -19,10 +19,10 @@ import numpy as np
 from . import count_ops
 
 
-def _prob(dim, system, nx, ny, fp32=0):
+def _prob(dim, system, nx, ny, fp32=0, order=3):
     return {"dim": dim, "system": system, "nx": nx, "ny": ny, "bc_x": 0, "bc_y": 0,
             "precision": fp32, "eps": 1e-20 if fp32 else 1e-40, "mu0": 1e-8 if fp32 else 1e-40,
-            "adv_speed": (1.0, 0.5)}
+            "adv_speed": (1.0, 0.5), "order": order}
 
 
 def _state(dim, system, nx, ny, seed=0):
@@ -38,8 +38,9 @@ def _state(dim, system, nx, ny, seed=0):
     return np.stack([rho, rho * u, rho * v, p / 0.4 + 0.5 * rho * (u * u + v * v)])
 
 
-def per_cell_and_interface(dim, system, direction, fp32=0):
-    """(a, b): FLOPs per cell (with ghosts) and per interface of one sweep."""
+def per_cell_and_interface(dim, system, direction, fp32=0, order=3):
+    """(a, b): FLOPs per cell (with its 2r ghosts) and per interface of one
+    sweep of the order-2r scheme."""
     out = []
     for n in (64, 128):
         if dim == 1:
@@ -49,13 +50,14 @@ def per_cell_and_interface(dim, system, direction, fp32=0):
         else:
             nx, ny = 4, n
         q = np.ascontiguousarray(_state(dim, system, nx, ny))
-        nir, c = count_ops(_prob(dim, system, nx, ny, fp32), q, 1 << direction)
+        nir, c = count_ops(_prob(dim, system, nx, ny, fp32, order), q, 1 << direction)
         flops = c["add"] + c["mul"] + c["div"] + c["sqrt"]
         lines = ny if direction == 0 else nx
         out.append((n, flops / lines))
     (n1, f1), (n2, f2) = out
-    # f = (n + 6) a + (n + 1) b, two equations
-    A = np.array([[n1 + 6, n1 + 1], [n2 + 6, n2 + 1]], dtype=float)
+    # f = (n + 2r) a + (n + 1) b, two equations
+    g = 2 * order
+    A = np.array([[n1 + g, n1 + 1], [n2 + g, n2 + 1]], dtype=float)
     a, b = np.linalg.solve(A, np.array([f1, f2]))
     return float(a), float(b)
 
@@ -76,6 +78,13 @@ def table():
                 else:
                     extra = diff + m + 5 * m      # difference + accumulate + stage
                 res[key] = {"cell_flux": round(a, 3), "interface": round(b, 3), "cell_update": extra}
+    # 2D Euler with the other orders (FP64)
+    for r in (2, 4, 5):
+        for d in (0, 1):
+            a, b = per_cell_and_interface(2, 1, d, 0, r)
+            extra = 8 if d == 0 else 8 + 4 + 20
+            res[f"euler_2d_r{r}_{'xy'[d]}"] = {"cell_flux": round(a, 3), "interface": round(b, 3),
+                                              "cell_update": extra}
     return res
 
 

@@ -60,3 +60,4 @@ inline za::CfgArg<T> make_cfg(const za_problem& p) {
 // weights, every mode; `a` as for the r = 3 kernels.
 void launch_x_order(za_ctx* c, int mode, const za::SweepArgs& a);
 void launch_y_order(za_ctx* c, int mode, const za::SweepArgs& a);
+int order_y_blocks_per_cu(const za_problem& p);

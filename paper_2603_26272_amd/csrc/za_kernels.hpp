@@ -535,6 +535,15 @@ template <int SYS, int M, class T, int MODE, int WV, int R = 3>
 __global__ __launch_bounds__(256) void k_sweep_y_any(SweepArgs a, CfgArg<T> cfg) {
   sweep_y_body<SYS, M, T, MODE, WV, R>(a, cfg, blockIdx.x, blockIdx.y, gridDim.x);
 }
+// Other orders with Z weights: an occupancy target per stencil width.
+template <int SYS, int M, class T, int MODE, int WV, int R, int WAVES>
+__global__ __launch_bounds__(256, WAVES) void k_sweep_x_r(SweepArgs a, CfgArg<T> cfg) {
+  sweep_x_body<SYS, M, T, MODE, WV, R>(a, cfg, blockIdx.x);
+}
+template <int SYS, int M, class T, int MODE, int WV, int R, int WAVES>
+__global__ __launch_bounds__(256, WAVES) void k_sweep_y_r(SweepArgs a, CfgArg<T> cfg) {
+  sweep_y_body<SYS, M, T, MODE, WV, R>(a, cfg, blockIdx.x, blockIdx.y, gridDim.x);
+}
 
 
 enum FinalKind { FIN_RHS = 0, FIN_STAGE0 = 1, FIN_STAGEK = 2 };

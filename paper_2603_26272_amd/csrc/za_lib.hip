@@ -286,9 +286,12 @@ static int pick_ytile(za_ctx* c) {
   const void* fn = p.system == ZA_EULER
                        ? reinterpret_cast<const void*>(&k_sweep_y<SYS_EULER, 4, T, MODE_STAGE, WV_Z1>)
                        : reinterpret_cast<const void*>(&k_sweep_y<SYS_ADV, 1, T, MODE_STAGE, WV_Z1>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, fn, 256, 0) != hipSuccess ||
-      blocks_per_cu < 1)
-    blocks_per_cu = 2;
+  if (order_of(p) != 3) {
+    blocks_per_cu = order_y_blocks_per_cu(p);
+  } else if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, fn, 256, 0) != hipSuccess) {
+    blocks_per_cu = 0;
+  }
+  if (blocks_per_cu < 1) blocks_per_cu = 2;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
     cus = 256;
   const long long strips = (p.nx + 63) / 64;

@@ -210,3 +210,23 @@ def test_order_arguments(dev):
     for order in (0, 3):   # 0 selects WENO-ZA6
         with Ctx(Problem(dim=1, nx=32, order=order)):
             pass
+
+
+@pytest.mark.parametrize("r,sizes", [(2, (16, 32, 64)), (3, (16, 32, 64)), (4, (16, 32, 64)), (5, (16, 32))])
+def test_gpu_rhs_convergence_order(dev, r, sizes):
+    """The GPU's 2D Euler right-hand side on the smooth density wave
+    rho = 1 + 0.2 sin(2 pi (x + y)), u = v = p = 1 converges to the exact
+    -(rho_x + rho_y) at order 2r (these grids sample no pair of equal
+    neighbours about an extremum, where r = 2 would lose accuracy)."""
+    import math
+    errs = []
+    for m in sizes:
+        P, q0 = W.smooth_wave_2d(m)
+        q = torch.from_numpy(q0).to(dev)
+        with Ctx(P.with_(order=r)) as ctx:
+            L = ctx.rhs(q).cpu().numpy()
+        x = W.centres(m, 0.0, 1.0)[None, :]
+        y = W.centres(m, 0.0, 1.0)[:, None]
+        errs.append(np.abs(L[0] + 0.8 * math.pi * np.cos(2 * math.pi * (x + y))).max())
+    rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
+    assert min(rates) > 2 * r - 0.6, (errs, rates)
