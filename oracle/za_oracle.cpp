@@ -537,12 +537,50 @@ static void euler_eigen(int m, int dir, R gm1, R u, R v, R H, R c, R* Rm, R* Lm)
  * alpha[s] = max |lambda_s| (s over the m characteristic fields) and
  * smax = max(|u_n| + c).  Returns 0 if the state is finite and physical,
  * 1 otherwise (rho <= 0, p <= 0 or a non-finite value). */
+/* Largest |f'(u)| of the Buckley-Leverett flux over u in [lo, hi].  f' =
+ * u (1-u) / (2 D^2), D = u^2 + (1-u)^2/4, has its extrema where
+ * (1-2u) D = 2 u (1-u) D', i.e. at the roots of 10 u^3 - 15 u^2 + 1 (one in
+ * each of (-1/2, 0), (0, 1/2), (1, 3/2)); the maximum over an interval is at
+ * an end point or at such a root inside it. */
+static double buckley_max_speed(double lo, double hi) {
+  auto fp = [](double u) { double D = u * u + 0.25 * (1 - u) * (1 - u); return 0.5 * u * (1 - u) / (D * D); };
+  auto cubic = [](double u) { return (10 * u - 15) * u * u + 1; };
+  double best = std::max(std::fabs(fp(lo)), std::fabs(fp(hi)));
+  const double brackets[3][2] = {{-0.5, 0.0}, {0.0, 0.5}, {1.0, 1.5}};
+  for (int b = 0; b < 3; ++b) {
+    double a = brackets[b][0], c = brackets[b][1];
+    const bool rising = cubic(a) < 0;
+    for (int it = 0; it < 200 && a < c; ++it) {     /* bisection to the last bit */
+      double mid = 0.5 * (a + c);
+      if (mid <= a || mid >= c) break;
+      if ((cubic(mid) < 0) == rising) a = mid; else c = mid;
+    }
+    const double root = a;
+    if (root > lo && root < hi) best = std::max(best, std::fabs(fp(root)));
+  }
+  return best;
+}
+
 static int wave_speeds(const orc_problem& P, const double* q, int dir, double* alpha, double* smax) {
   const int m = ncomp(P);
   const size_t ncell = (size_t)P.nx * P.ny;
   int bad = 0;
   for (int s = 0; s < 4; ++s) alpha[s] = 0;
   *smax = 0;
+  if (P.system == SYS_BUCKLEY) {
+    /* non-convex flux: the LF speed is max |f'| over the range of the data
+     * (the data's own values can all sit where f' vanishes, e.g. u in {0, 1}) */
+    double lo = INFINITY, hi = -INFINITY;
+    for (size_t i = 0; i < ncell; ++i) {
+      double u = q[i];
+      if (u != u) bad = 1;
+      lo = std::min(lo, u);
+      hi = std::max(hi, u);
+    }
+    double a = bad ? 0.0 : buckley_max_speed(lo, hi);
+    alpha[0] = a; *smax = a;
+    return bad;
+  }
   if (P.system != SYS_EULER) {
     double a = 0;
     for (size_t i = 0; i < ncell; ++i) {

@@ -113,6 +113,13 @@ __device__ __forceinline__ void cell_speeds(const double (&Q)[M], const Phys& ph
     r[3] = wave_max(r[3], fabs(v - c));
     r[4] = wave_max(r[4], fabs(v));
     r[5] = wave_max(r[5], fabs(v + c));
+  } else if (SYS == SYS_BUCKLEY) {
+    // non-convex flux: keep the data range (max u, max -u); the final
+    // reduction takes max |f'| over it
+    const double u = Q[0];
+    if (!((u - u) == 0.0)) { r[0] = __builtin_huge_val(); return; }
+    r[0] = wave_max(r[0], u);
+    r[1] = wave_max(r[1], -u);
   } else {
     const double u = Q[0];
     if (!((u - u) == 0.0)) { r[0] = __builtin_huge_val(); return; }
@@ -121,6 +128,33 @@ __device__ __forceinline__ void cell_speeds(const double (&Q)[M], const Phys& ph
     r[0] = wave_max(r[0], ax); r[2] = r[0];
     r[3] = wave_max(r[3], ay); r[5] = r[3];
   }
+}
+
+// Largest |f'(u)| of the Buckley-Leverett flux for u in [lo, hi]:
+// f'(u) = u (1-u) / (2 D^2), D = u^2 + (1-u)^2/4, is extremal where
+// 10 u^3 - 15 u^2 + 1 = 0 (one root in each of (-1/2, 0), (0, 1/2),
+// (1, 3/2)); the maximum is at an end of the interval or at such a root
+// inside it.  The roots are found by bisection to the last bit.
+__device__ __forceinline__ double buckley_dfdu(double u) {
+  const double w = 1.0 - u;
+  const double D = fma(u, u, 0.25 * w * w);
+  return 0.5 * u * w / (D * D);
+}
+__device__ inline double buckley_max_speed(double lo, double hi) {
+  double best = fmax(fabs(buckley_dfdu(lo)), fabs(buckley_dfdu(hi)));
+  const double b0[3] = {-0.5, 0.0, 1.0}, b1[3] = {0.0, 0.5, 1.5};
+  for (int k = 0; k < 3; ++k) {
+    double a = b0[k], c = b1[k];
+    const bool neg_at_a = fma(fma(10.0, a, -15.0), a * a, 1.0) < 0.0;
+    for (int it = 0; it < 200; ++it) {
+      const double m = 0.5 * (a + c);
+      if (!(m > a && m < c)) break;
+      const bool neg = fma(fma(10.0, m, -15.0), m * m, 1.0) < 0.0;
+      if (neg == neg_at_a) a = m; else c = m;
+    }
+    if (a > lo && a < hi) best = fmax(best, fabs(buckley_dfdu(a)));
+  }
+  return best;
 }
 
 // Index of the calling wavefront in its block, as a wave-uniform (scalar)
@@ -163,7 +197,7 @@ __global__ __launch_bounds__(256) void k_wave_partial(const double* __restrict__
   if (check_active && !ctl->active) return;
   double r[NPART];
 #pragma unroll
-  for (int i = 0; i < NPART; ++i) r[i] = 0.0;
+  for (int i = 0; i < NPART; ++i) r[i] = -__builtin_huge_val();
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncell; i += (size_t)gridDim.x * blockDim.x) {
     double Q[M];
 #pragma unroll
@@ -318,7 +352,7 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
   const int i = c0 + lane;
   double rs[NPART];
 #pragma unroll
-  for (int t = 0; t < NPART; ++t) rs[t] = 0.0;
+  for (int t = 0; t < NPART; ++t) rs[t] = -__builtin_huge_val();
   if (live && lane < XS_CELLS && i < nx) {
     const size_t idx = row + i;
     if (MODE == MODE_LX) {
@@ -507,7 +541,7 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
   if (a.check_active && !a.ctl->active) return;
   double rs[NPART];
 #pragma unroll
-  for (int t = 0; t < NPART; ++t) rs[t] = 0.0;
+  for (int t = 0; t < NPART; ++t) rs[t] = -__builtin_huge_val();
   const int ny = a.g.ny;
   const int nb = (ny + a.ytile - 1) / a.ytile;
   const int y0 = (int)((long long)by * ny / nb), ylast = (int)((long long)(by + 1) * ny / nb);
@@ -549,10 +583,10 @@ __global__ __launch_bounds__(256, WAVES) void k_sweep_y_r(SweepArgs a, CfgArg<T>
 enum FinalKind { FIN_RHS = 0, FIN_STAGE0 = 1, FIN_STAGEK = 2 };
 
 __device__ __forceinline__ void wave_final_body(const double* __restrict__ part, int nblk, DevCtl* ctl,
-                                                const Geom& g, const Phys& ph, int dim, int kind, int is_euler) {
+                                                const Geom& g, const Phys& ph, int dim, int kind, int sys) {
   double r[NPART];
 #pragma unroll
-  for (int i = 0; i < NPART; ++i) r[i] = 0.0;
+  for (int i = 0; i < NPART; ++i) r[i] = -__builtin_huge_val();
   for (int b = threadIdx.x; b < nblk; b += 64) {
 #pragma unroll
     for (int i = 0; i < NPART; ++i) r[i] = wave_max(r[i], part[(size_t)b * NPART + i]);
@@ -564,8 +598,12 @@ __device__ __forceinline__ void wave_final_body(const double* __restrict__ part,
   if (threadIdx.x != 0) return;
   if (kind != FIN_RHS && !ctl->active) return;
   const bool bad = !(r[0] < __builtin_huge_val());
-  const double sx = wave_max(r[0], r[2]), sy = wave_max(r[3], r[5]);
-  if (is_euler) {
+  double sx = wave_max(r[0], r[2]), sy = wave_max(r[3], r[5]);
+  if (sys == SYS_BUCKLEY) {
+    sx = sy = bad ? 0.0 : buckley_max_speed(-r[1], r[0]);
+    ctl->alpha[0][0] = sx;
+    ctl->alpha[1][0] = sy;
+  } else if (sys == SYS_EULER) {
     if (ph.lf_scalar) {
       for (int s = 0; s < 4; ++s) { ctl->alpha[0][s] = sx; ctl->alpha[1][s] = sy; }
     } else {
@@ -606,8 +644,8 @@ __device__ __forceinline__ void wave_final_body(const double* __restrict__ part,
 
 template <int M>
 __global__ __launch_bounds__(64) void k_wave_final(const double* __restrict__ part, int nblk, DevCtl* ctl,
-                                                   Geom g, Phys ph, int dim, int kind, int is_euler) {
-  wave_final_body(part, nblk, ctl, g, ph, dim, kind, is_euler);
+                                                   Geom g, Phys ph, int dim, int kind, int sys) {
+  wave_final_body(part, nblk, ctl, g, ph, dim, kind, sys);
 }
 
 __device__ __forceinline__ void step_end_body(DevCtl* ctl) {

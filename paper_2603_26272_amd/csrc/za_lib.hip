@@ -223,7 +223,7 @@ static void launch_y(za_ctx* c, int mode, const SweepArgs& a) {
 
 static void launch_final(za_ctx* c, int kind, int nblk) {
   hipLaunchKernelGGL((k_wave_final<4>), dim3(1), dim3(64), 0, c->stream, c->part, nblk, c->ctl, c->geom, c->ph,
-                     c->prob.dim, kind, c->prob.system == ZA_EULER ? 1 : 0);
+                     c->prob.dim, kind, (int)c->prob.system);
 }
 
 // Stand-alone wave-speed reduction of q followed by the final reduction.

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(64) void kb_final(const BatchTable* __restrict__ ta
   const int s = blockIdx.x;
   if (s >= tab->n) return;
   const SlotDesc& d = tab->s[s];
-  wave_final_body(d.part, d.stage_blocks, d.ctl, d.g, d.ph, dim, kind, 1);
+  wave_final_body(d.part, d.stage_blocks, d.ctl, d.g, d.ph, dim, kind, SYS_EULER);
 }
 
 __global__ __launch_bounds__(64) void kb_step_end(const BatchTable* __restrict__ tab) {

@@ -18,6 +18,11 @@ data, and these generators stand in for them):
   * ``entropy_wave_1d``  - 1D Euler density wave, periodic.
   * ``shock_tube``       - Sod / Lax / 123 tubes of the paper's 1D table.
   * ``riemann_config3``  - the paper's 2D Riemann configuration 3.
+  * ``multiwave``        - u_t + u_x = 0 with the Gaussian / square / triangle /
+                           semi-ellipse initial data of Section 4.1 (N = 400,
+                           T = 20 on periodic [-1, 1]).
+  * ``burgers_sine``     - Burgers u0 = 1/2 + sin(2 pi x) (tab:scalar_fluxes).
+  * ``buckley_step``     - Buckley-Leverett step data (tab:scalar_fluxes).
   * ``serving_stream``   - a Poisson stream of mixed 1D / 2D solve requests.
 """
 import math
@@ -26,7 +31,7 @@ from typing import List, Optional, Tuple
 
 import numpy as np
 
-from .problem import (ADVECTION, DT_CFL, DT_CFL_H2, EULER, FP32_RECON, FP64,
+from .problem import (ADVECTION, BUCKLEY, BURGERS, DT_CFL, DT_CFL_H2, EULER, FP32_RECON, FP64,
                       PERIODIC, TRANSMISSIVE, Problem)
 
 GAMMA = 1.4
@@ -239,3 +244,85 @@ def serving_stream(lam: float, n_requests: int = 512, seed: Optional[int] = None
             P = P.fp32()
         out.append(Request(i, t, P, q, steps, "smooth" if smooth else "riemann"))
     return out
+
+
+# --------------------------------------------------------------------------
+# Scalar laws of Section 4.1.  Domains and boundaries the paper leaves open
+# are readings: Burgers on periodic [0, 1] (one period of the sine),
+# Buckley-Leverett on [-1, 1] with transmissive boundaries (the waves stay
+# inside up to T = 0.3).
+MULTIWAVE_T = 20.0
+
+
+def multiwave_exact(x: np.ndarray) -> np.ndarray:
+    """The multi-wave initial data (= the exact solution at T = 20, ten
+    periods later): Gaussian, square, triangle, semi-ellipse."""
+    delta, z, alpha, y = 0.005, -0.7, 10.0, 0.5
+    beta = math.log(2.0) / (36.0 * delta * delta)
+
+    def G(zz):
+        return np.exp(-beta * (x - zz) ** 2)
+
+    def F(yy):
+        return np.sqrt(np.maximum(1.0 - alpha * alpha * (x - yy) ** 2, 0.0))
+
+    q = np.zeros_like(x)
+    m = (x >= -0.8) & (x <= -0.6)
+    q[m] = ((G(z - delta) + 4.0 * G(z) + G(z + delta)) / 6.0)[m]
+    q[(x >= -0.4) & (x <= -0.2)] = 1.0
+    m = (x >= 0.0) & (x <= 0.2)
+    q[m] = (1.0 - np.abs(10.0 * (x - 0.1)))[m]
+    m = (x >= 0.4) & (x <= 0.6)
+    q[m] = ((F(y - delta) + 4.0 * F(y) + F(y + delta)) / 6.0)[m]
+    return q
+
+
+def multiwave(N: int = 400) -> Tuple[Problem, np.ndarray]:
+    P = Problem(dim=1, system=ADVECTION, nx=N, ny=1, xlo=-1.0, xhi=1.0, bc_x=PERIODIC,
+                adv_speed=(1.0, 0.0), cfl=0.45)
+    return P, multiwave_exact(centres(N, -1.0, 1.0)).reshape(1, 1, N)
+
+
+BURGERS_T = 0.2
+
+
+def burgers_sine(N: int = 80) -> Tuple[Problem, np.ndarray]:
+    P = Problem(dim=1, system=BURGERS, nx=N, ny=1, xlo=0.0, xhi=1.0, bc_x=PERIODIC, cfl=0.45)
+    x = centres(N, 0.0, 1.0)
+    return P, (0.5 + np.sin(2.0 * math.pi * x)).reshape(1, 1, N)
+
+
+def burgers_sine_exact(x: np.ndarray, t: float) -> np.ndarray:
+    """Entropy solution of u_t + (u^2/2)_x = 0, u0 = 1/2 + sin(2 pi x) on
+    periodic [0, 1], by characteristics.  With v = u - 1/2 and x' = x - t/2
+    the data are odd about x' = 0, so the shock that forms at t = 1/(2 pi)
+    stays at x' = 1/2; for x' in [-1/2, 1/2) the value comes from the foot xi
+    in (-1/2, 1/2) with xi + t sin(2 pi xi) = x', taken on the branch where
+    that map is increasing (|xi| < xi_c, cos(2 pi xi_c) = -1/(2 pi t))."""
+    if t * 2.0 * math.pi < 1.0:
+        lim = 0.5
+    else:
+        lim = math.acos(-1.0 / (2.0 * math.pi * t)) / (2.0 * math.pi)
+    out = np.empty_like(x, dtype=float)
+    for i, xv in enumerate(np.asarray(x, dtype=float)):
+        xp = ((xv - 0.5 * t) + 0.5) % 1.0 - 0.5
+        a, b = -lim, lim
+        for _ in range(200):
+            m = 0.5 * (a + b)
+            if m <= a or m >= b:
+                break
+            if m + t * math.sin(2.0 * math.pi * m) < xp:
+                a = m
+            else:
+                b = m
+        out[i] = 0.5 + math.sin(2.0 * math.pi * a)
+    return out
+
+
+BUCKLEY_T = 0.3
+
+
+def buckley_step(N: int = 200) -> Tuple[Problem, np.ndarray]:
+    P = Problem(dim=1, system=BUCKLEY, nx=N, ny=1, xlo=-1.0, xhi=1.0, bc_x=TRANSMISSIVE, cfl=0.45)
+    x = centres(N, -1.0, 1.0)
+    return P, np.where((x >= -0.5) & (x <= 0.0), 1.0, 0.0).reshape(1, 1, N)
