@@ -355,6 +355,67 @@ def study_orders(torch, Context, n=2048, steps=20):
     return out
 
 
+def study_scalar(torch, Context):
+    """Scalar laws of Section 4.1 on the GPU: the multi-wave advection run
+    (N = 400, T = 20) against its exact solution, Burgers (N = 80, T = 0.2)
+    against the characteristic solution away from the shock, Buckley-Leverett
+    (N = 200, T = 0.3) against an N = 3200 run of the same code, and the
+    throughput of 2D scalar sweeps at 2048^2 (advection and Buckley-Leverett,
+    20 steps)."""
+    import numpy as np
+
+    from paper_2603_26272_amd import workloads as W
+    from paper_2603_26272_amd.problem import ADVECTION, BUCKLEY, PERIODIC, Problem
+    out = {"study": "scalar laws (Section 4.1)"}
+
+    def solve(P, q0, T):
+        q = torch.from_numpy(np.ascontiguousarray(q0)).to("cuda")
+        with Context(P) as ctx:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = ctx.solve(q, T)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        return q.cpu().numpy()[0, 0], info, wall
+
+    P, q0 = W.multiwave(400)
+    q, info, wall = solve(P, q0, W.MULTIWAVE_T)
+    x = W.centres(400, -1.0, 1.0)
+    e = np.abs(q - W.multiwave_exact(x))
+    g = (x > -0.8) & (x < -0.6)
+    out["multiwave"] = {"N": 400, "T": W.MULTIWAVE_T, "steps": info["steps"], "wall_s": wall,
+                        "l1": float(e.mean() * 2.0), "linf": float(e.max()), "gaussian_linf": float(e[g].max()),
+                        "max": float(q.max()), "min": float(q.min())}
+    P, q0 = W.burgers_sine(80)
+    q, info, wall = solve(P, q0, W.BURGERS_T)
+    x = W.centres(80, 0.0, 1.0)
+    e = np.abs(q - W.burgers_sine_exact(x, W.BURGERS_T))
+    xs = 0.5 + 0.5 * W.BURGERS_T
+    far = np.abs(((x - xs) + 0.5) % 1.0 - 0.5) > 0.1
+    out["burgers"] = {"N": 80, "T": W.BURGERS_T, "steps": info["steps"], "linf_away_from_shock": float(e[far].max()),
+                      "linf_near_shock": float(e[~far].max())}
+    P, q0 = W.buckley_step(200)
+    q, info, wall = solve(P, q0, W.BUCKLEY_T)
+    Pf, qf = W.buckley_step(3200)
+    rf, _, _ = solve(Pf, qf, W.BUCKLEY_T)
+    out["buckley"] = {"N": 200, "T": W.BUCKLEY_T, "steps": info["steps"],
+                      "l1_vs_N3200": float(np.abs(q - rf.reshape(200, 16).mean(axis=1)).mean() * 2.0),
+                      "max": float(q.max()), "min": float(q.min())}
+    n = 2048
+    x = W.centres(n, 0.0, 1.0)[None, :]
+    y = W.centres(n, 0.0, 1.0)[:, None]
+    base = 0.5 + 0.4 * np.sin(2 * np.pi * (x + 2 * y)) + 0.3 * (x > 0.5) * (y < 0.4)
+    rows = []
+    for name, system in (("advection_2d", ADVECTION), ("buckley_2d", BUCKLEY)):
+        P = Problem(dim=2, system=system, nx=n, ny=n, bc_x=PERIODIC, bc_y=PERIODIC, adv_speed=(1.0, 0.5))
+        _, wall, info, avg_ms, counts = run_gpu(P, np.ascontiguousarray(base.reshape(1, n, n)), 20, 2, torch,
+                                                Context)
+        rows.append({"workload": f"{name} {n}x{n} FP64", "IR_s": 3 * ir_per_rhs(n, n) * 20 / wall,
+                     "ms_per_step": wall / 20 * 1e3, "x_ms": avg_ms[0], "y_ms": avg_ms[1]})
+    out["throughput_2d"] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -370,7 +431,7 @@ def main():
                     help="Poisson rates (req/s) of the serving leg; the full sweep is 10,25,50,100,200")
     ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--serving-budget-gb", type=float, default=4.0)
-    ap.add_argument("--study", choices=["c0", "c1", "c3", "orders", "serving"], default=None,
+    ap.add_argument("--study", choices=["c0", "c1", "c3", "orders", "scalar", "serving"], default=None,
                     help="run one workload study instead of the benchmark line")
     args = ap.parse_args()
 
@@ -395,6 +456,8 @@ def main():
             res = study_c3(torch, Context)
         elif args.study == "orders":
             res = study_orders(torch, Context)
+        elif args.study == "scalar":
+            res = study_scalar(torch, Context)
         else:
             rates = [float(x) for x in args.serving_rates.split(",") if x]
             res = {"study": "serving sweep", "hbm_budget_gb": args.serving_budget_gb,
