@@ -87,6 +87,13 @@ typedef struct {
                            /* eighth- and tenth-order schemes of Appendix A,  */
                            /* FP64 only (ZA_ERR_UNSUPPORTED otherwise; the    */
                            /* server takes r = 3 only)                        */
+  int32_t pp_limiter;      /* 1: positivity-preserving flux limiter (Euler,   */
+                           /* FP64) in every stage of za_step / za_solve and  */
+                           /* the server: each face flux is blended with the  */
+                           /* first-order LF flux so that density and         */
+                           /* pressure stay >= 1e-13 (Hu, Adams and Shu 2013, */
+                           /* cited in Section 4.3; needs cfl <= 0.5); the    */
+                           /* right-hand-side calls are not limited           */
 } za_problem;
 
 typedef struct za_ctx za_ctx;

@@ -40,6 +40,7 @@ class _Problem(C.Structure):
         ("lf", C.c_int32),
         ("linear_weights", C.c_int32),
         ("order", C.c_int32),
+        ("pp_limiter", C.c_int32),
     ]
 
 
@@ -126,6 +127,7 @@ def _problem(pb) -> _Problem:
     P.lf = int(_get(pb, "lf", 0))
     P.linear_weights = int(_get(pb, "linear_weights", 0))
     P.order = int(_get(pb, "order", 3))
+    P.pp_limiter = int(_get(pb, "pp_limiter", 0))
     _ensure_order(P.order)
     return P
 

@@ -424,6 +424,7 @@ typedef struct {
   int32_t lf;
   int32_t linear_weights;
   int32_t order;          /* r of the order-2r scheme (0 or 3: WENO-ZA6) */
+  int32_t pp_limiter;     /* 1: positivity-preserving flux limiter in steps */
 } orc_problem;
 }
 
@@ -770,16 +771,98 @@ static int sweep_fluxes(const Ctx& C, const double* q, int dir, const double* al
   return 0;
 }
 
-/* L(Q) = -(F_{i+1/2} - F_{i-1/2})/dx  [+ the same in y]   (eq:hyperbolic_1D_scalar_h,
- * dimension by dimension in 2D, Section 4.3). */
-template <class R>
-static int rhs_impl(const Ctx& C, const double* q, double* rhs) {
+/* ------------------------------------------------------------------------ */
+/* Positivity-preserving flux limiter for the Euler equations, after Hu,     */
+/* Adams and Shu (J. Comput. Phys. 242, 2013), which the paper cites for its */
+/* shock-diffraction test (Section 4.3).  A forward-Euler stage with step dt */
+/* is a convex combination of one-dimensional updates, and each cell's      */
+/* update of one direction is the mean of two "half" states, one per face:  */
+/*   U_i - 2 mu F_{i+1/2}  and  U_{i+1} + 2 mu F_{i+1/2},                   */
+/* mu = dt S / s_dir with s_dir = max(|u_n| + c) of that direction and     */
+/* S = sum over directions of s_d / dx_d (1D: mu = dt/dx).  With the first- */
+/* order global Lax-Friedrichs flux in place of F both half states stay     */
+/* positive whenever dt S <= 1/2.  Each face's flux becomes                  */
+/*   F~ = F_LF + theta (F - F_LF),                                           */
+/* theta in [0, 1] the largest value (up to the bounds below) that keeps    */
+/* density and pressure of both half states >= eps = 1e-13: density is      */
+/* linear in theta (exact bound); pressure is concave in the state, so the  */
+/* chord from the LF half state to the density-limited one is a lower bound */
+/* and gives theta_p in closed form.  Faces whose high-order half states are */
+/* admissible keep theta = 1.  Only stages (with a dt) are limited.          */
+/* ------------------------------------------------------------------------ */
+static const double PP_EPS = 1e-13;
+
+static double pp_pressure(int m, double gm1, const double* U) {
+  double k = U[1] * U[1];
+  if (m == 4) k += U[2] * U[2];
+  return gm1 * (U[m - 1] - 0.5 * k / U[0]);
+}
+
+/* theta keeping A + theta B admissible (A: the LF half state) */
+static double pp_theta(int m, double gm1, const double* A, const double* B) {
+  const double rA = A[0], pA = (rA > 0) ? pp_pressure(m, gm1, A) : -1.0;
+  if (!(rA >= PP_EPS) || !(pA >= PP_EPS)) return 0.0;
+  double th = 1.0;
+  const double r1 = rA + B[0];
+  if (r1 < PP_EPS) th = (rA - PP_EPS) / (rA - r1);
+  double U1[4];
+  for (int c = 0; c < m; ++c) U1[c] = A[c] + th * B[c];
+  const double p1 = pp_pressure(m, gm1, U1);
+  if (p1 < PP_EPS) th = th * (pA - PP_EPS) / (pA - p1);
+  return th;
+}
+
+/* Limit the interface fluxes F of direction dir of state q in place. */
+static void pp_limit(const Ctx& C, const double* q, int dir, double dt, double S, double s_dir, double* F) {
   const orc_problem& P = C.P;
   const int m = C.m, nx = P.nx, ny = P.ny;
-  double ax[4], ay[4], sx, sy;
+  const double gm1 = P.gamma - 1.0;
+  const double mu = dt * S / s_dir;
+  const int n = dir == 0 ? nx : ny, lines = dir == 0 ? ny : nx;
+  const int bc = dir == 0 ? P.bc_x : P.bc_y;
+#pragma omp parallel for schedule(static)
+  for (int l = 0; l < lines; ++l) {
+    for (int k = 0; k <= n; ++k) {
+      const int jl = bc_index(k - 1, n, bc), jr = bc_index(k, n, bc);
+      const size_t il = dir == 0 ? (size_t)l * nx + jl : (size_t)jl * nx + l;
+      const size_t ir = dir == 0 ? (size_t)l * nx + jr : (size_t)jr * nx + l;
+      double QL[4], QR[4], FL[4], FR[4], Fh[4], Flf[4];
+      for (int c = 0; c < m; ++c) { QL[c] = q[c * C.ncell + il]; QR[c] = q[c * C.ncell + ir]; }
+      euler_flux<double>(m, dir, gm1, QL, FL);
+      euler_flux<double>(m, dir, gm1, QR, FR);
+      const size_t fi = dir == 0 ? (size_t)l * (nx + 1) + k : (size_t)k * nx + l;
+      const size_t fs = dir == 0 ? (size_t)ny * (nx + 1) : (size_t)(ny + 1) * nx;
+      double AL[4], BL[4], AR[4], BR[4];
+      for (int c = 0; c < m; ++c) {
+        Fh[c] = F[c * fs + fi];
+        Flf[c] = 0.5 * (FL[c] + FR[c] - s_dir * (QR[c] - QL[c]));
+        AL[c] = QL[c] - 2.0 * mu * Flf[c];
+        BL[c] = -2.0 * mu * (Fh[c] - Flf[c]);
+        AR[c] = QR[c] + 2.0 * mu * Flf[c];
+        BR[c] = 2.0 * mu * (Fh[c] - Flf[c]);
+      }
+      const double th = std::min(pp_theta(m, gm1, AL, BL), pp_theta(m, gm1, AR, BR));
+      if (th < 1.0)
+        for (int c = 0; c < m; ++c) F[c * fs + fi] = Flf[c] + th * (Fh[c] - Flf[c]);
+    }
+  }
+}
+
+/* L(Q) = -(F_{i+1/2} - F_{i-1/2})/dx  [+ the same in y]   (eq:hyperbolic_1D_scalar_h,
+ * dimension by dimension in 2D, Section 4.3).  dt > 0 with the limiter on:
+ * the fluxes of the stage Q + dt L(Q) are limited first. */
+template <class R>
+static int rhs_impl(const Ctx& C, const double* q, double* rhs, double dt = 0.0) {
+  const orc_problem& P = C.P;
+  const int m = C.m, nx = P.nx, ny = P.ny;
+  double ax[4], ay[4], sx, sy = 0;
   int bad = wave_speeds(P, q, 0, ax, &sx);
+  if (P.dim == 2) bad |= wave_speeds(P, q, 1, ay, &sy);
+  const bool pp = P.pp_limiter && P.system == SYS_EULER && dt > 0 && !bad;
+  const double S = sx / C.dx + (P.dim == 2 ? sy / C.dy : 0.0);
   std::vector<double> fx((size_t)m * ny * (nx + 1));
   sweep_fluxes<R>(C, q, 0, ax, fx.data());
+  if (pp) pp_limit(C, q, 0, dt, S, sx, fx.data());
   for (int c = 0; c < m; ++c)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
@@ -787,9 +870,9 @@ static int rhs_impl(const Ctx& C, const double* q, double* rhs) {
         rhs[(size_t)c * C.ncell + (size_t)y * nx + x] = -(f[x + 1] - f[x]) / C.dx;
       }
   if (P.dim == 2) {
-    bad |= wave_speeds(P, q, 1, ay, &sy);
     std::vector<double> fy((size_t)m * (ny + 1) * nx);
     sweep_fluxes<R>(C, q, 1, ay, fy.data());
+    if (pp) pp_limit(C, q, 1, dt, S, sy, fy.data());
     for (int c = 0; c < m; ++c)
       for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
@@ -800,8 +883,8 @@ static int rhs_impl(const Ctx& C, const double* q, double* rhs) {
   return bad;
 }
 
-static int rhs_any(const Ctx& C, const double* q, double* rhs) {
-  return C.P.recon_fp32 ? rhs_impl<float>(C, q, rhs) : rhs_impl<double>(C, q, rhs);
+static int rhs_any(const Ctx& C, const double* q, double* rhs, double dt = 0.0) {
+  return C.P.recon_fp32 ? rhs_impl<float>(C, q, rhs, dt) : rhs_impl<double>(C, q, rhs, dt);
 }
 
 /* CFL time step from the current state (Section 4, reading for 2D). */
@@ -825,11 +908,11 @@ static double cfl_dt(const Ctx& C, const double* q, int* bad) {
 static int rk3_step(const Ctx& C, double* q, double dt) {
   const size_t n = (size_t)C.m * C.ncell;
   std::vector<double> L(n), q1(n), q2(n);
-  int bad = rhs_any(C, q, L.data());
+  int bad = rhs_any(C, q, L.data(), dt);
   for (size_t i = 0; i < n; ++i) q1[i] = q[i] + dt * L[i];
-  bad |= rhs_any(C, q1.data(), L.data());
+  bad |= rhs_any(C, q1.data(), L.data(), dt);
   for (size_t i = 0; i < n; ++i) q2[i] = 0.75 * q[i] + 0.25 * (q1[i] + dt * L[i]);
-  bad |= rhs_any(C, q2.data(), L.data());
+  bad |= rhs_any(C, q2.data(), L.data(), dt);
   for (size_t i = 0; i < n; ++i) q[i] = (1.0 / 3.0) * q[i] + (2.0 / 3.0) * (q2[i] + dt * L[i]);
   for (size_t i = 0; i < n; ++i) if (!std::isfinite(q[i])) bad = 1;
   return bad;

@@ -47,6 +47,7 @@ struct Phys {
   double cfl;
   int dt_rule;            // 0 CFL, 1 CFL h^2
   int lf_scalar;          // 1: one LF speed for every field
+  int pp;                 // 1: positivity-preserving flux limiter in stages
 };
 
 // Ghost cells: periodic wrap or transmissive clamp (three per side).
@@ -238,12 +239,97 @@ __device__ __forceinline__ void stage_cell(const double* __restrict__ base, size
   }
 }
 
+// ---------------------------------------------------------------------------
+// Positivity-preserving flux limiter (Euler, FP64 stages), after Hu, Adams
+// and Shu (J. Comput. Phys. 242, 2013), cited by the paper for its shock
+// diffraction test (Section 4.3).  A stage Q + dt L(Q) is a convex
+// combination of 1D updates, and each direction's update of a cell is the
+// mean of two half states, one per face: Q_i - 2 mu F_{i+1/2} and
+// Q_{i+1} + 2 mu F_{i+1/2}, mu = dt S / s_dir (s_dir = max(|u_n| + c) of the
+// direction, S = sum_d s_d / dx_d; 1D: mu = dt / dx).  With the first-order
+// global LF flux both half states are positive for dt S <= 1/2; the face
+// flux becomes F_LF + theta (F - F_LF) with the largest theta in [0, 1] (up
+// to the bounds) keeping density and pressure of both half states >= 1e-13:
+// density is linear in theta, pressure concave in the state, so the chord
+// from the LF half state to the density-limited one bounds it from below.
+// Works in the sweep-normal frame (density and pressure do not depend on the
+// order of the momentum components).
+// ---------------------------------------------------------------------------
+constexpr double PP_EPS = 1e-13;
+
+template <int M>
+__device__ __forceinline__ double pp_pressure(const double (&U)[M], double gm1) {
+  double k = U[1] * U[1];
+  if (M == 4) k = fma(U[2 % M], U[2 % M], k);
+  return gm1 * (U[M - 1] - 0.5 * k / U[0]);
+}
+
+// theta keeping A + theta B admissible (A: a half state of the LF flux)
+template <int M>
+__device__ __forceinline__ double pp_theta(const double (&A)[M], const double (&B)[M], double gm1) {
+  const double rA = A[0];
+  const double pA = rA > 0.0 ? pp_pressure<M>(A, gm1) : -1.0;
+  if (!(rA >= PP_EPS) || !(pA >= PP_EPS)) return 0.0;
+  double th = 1.0;
+  const double r1 = rA + B[0];
+  if (r1 < PP_EPS) th = (rA - PP_EPS) / (rA - r1);
+  double U1[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) U1[c] = fma(th, B[c], A[c]);
+  const double p1 = pp_pressure<M>(U1, gm1);
+  if (p1 < PP_EPS) th = th * (pA - PP_EPS) / (pA - p1);
+  return th;
+}
+
+// Limit the sweep-frame flux F of the face between the records at oL, oR.
+template <int M>
+__device__ void pp_limit_face(const double* __restrict__ rec, int fs, int oL, int oR, double gm1, double s,
+                              double mu, double (&F)[M]) {
+  typedef RecLayout<M> Lo;
+  double QL[M], QR[M], FL[M], FR[M];
+  QL[0] = rec[Lo::Q0 * fs + oL];  QR[0] = rec[Lo::Q0 * fs + oR];
+  QL[1] = rec[Lo::Q1 * fs + oL];  QR[1] = rec[Lo::Q1 * fs + oR];
+  QL[M - 1] = rec[Lo::E * fs + oL];  QR[M - 1] = rec[Lo::E * fs + oR];
+  FL[0] = QL[1];  FR[0] = QR[1];
+  FL[1] = rec[Lo::F1 * fs + oL];  FR[1] = rec[Lo::F1 * fs + oR];
+  FL[M - 1] = rec[Lo::F3 * fs + oL];  FR[M - 1] = rec[Lo::F3 * fs + oR];
+  if (M == 4) {
+    QL[2 % M] = rec[(M == 4 ? Lo::Q2 : 0) * fs + oL];  QR[2 % M] = rec[(M == 4 ? Lo::Q2 : 0) * fs + oR];
+    FL[2 % M] = rec[(M == 4 ? Lo::F2 : 0) * fs + oL];  FR[2 % M] = rec[(M == 4 ? Lo::F2 : 0) * fs + oR];
+  }
+  double Flf[M], AL[M], BL[M], AR[M], BR[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    Flf[c] = 0.5 * (FL[c] + FR[c] - s * (QR[c] - QL[c]));
+    const double d = 2.0 * mu * (F[c] - Flf[c]);
+    AL[c] = QL[c] - 2.0 * mu * Flf[c];
+    BL[c] = -d;
+    AR[c] = QR[c] + 2.0 * mu * Flf[c];
+    BR[c] = d;
+  }
+  const double th = fmin(pp_theta<M>(AL, BL, gm1), pp_theta<M>(AR, BR, gm1));
+  if (th < 1.0) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) F[c] = fma(th, F[c] - Flf[c], Flf[c]);
+  }
+}
+
+// Limiter step size of a sweep in direction DIR for the stage in progress
+// (0: no limiting): mu = dt S / s_DIR.
+template <int DIR>
+__device__ __forceinline__ double pp_mu(const DevCtl* ctl, const Geom& g, bool two_d) {
+  const double sx = ctl->smax[0], sy = two_d ? ctl->smax[1] : 0.0;
+  const double S = fma(sx, g.inv_dx, two_d ? sy * g.inv_dy : 0.0);
+  const double sd = DIR == 0 ? sx : sy;
+  return sd > 0.0 ? ctl->dt * S / sd : 0.0;
+}
+
 // Interface flux from the records of its six-point stencil; the result is
 // returned in the state's own component order.
 template <int SYS, int M, int DIR, class T, int WV, int R = 3>
 __device__ __forceinline__ void stencil_flux(const T* __restrict__ rec, int fs, const int (&off)[2 * R],
                                              const Phys& ph, const DevCtl* ctl, const WeightCfg<T>& cfg,
-                                             T (&Fh)[M]) {
+                                             T (&Fh)[M], double pp_mu_dir = 0.0) {
   if (SYS == SYS_EULER) {
     constexpr int MM = (M == 1 ? 4 : M);
     T al[MM];
@@ -255,6 +341,17 @@ __device__ __forceinline__ void stencil_flux(const T* __restrict__ rec, int fs, 
     }
     T F[MM];
     euler_flux<T, MM, WV, R>(rec, fs, off, (T)ph.gm1, al, cfg, F);
+    if constexpr (sizeof(T) == sizeof(double)) {
+      if (pp_mu_dir > 0.0) {
+        double Fd[MM];
+#pragma unroll
+        for (int c = 0; c < MM; ++c) Fd[c] = (double)F[c];
+        pp_limit_face<MM>(reinterpret_cast<const double*>(rec), fs, off[R - 1], off[R], ph.gm1, ctl->smax[DIR],
+                          pp_mu_dir, Fd);
+#pragma unroll
+        for (int c = 0; c < MM; ++c) F[c] = (T)Fd[c];
+      }
+    }
     if (MM == 4 && DIR == 1) {
       Fh[0] = F[0]; Fh[1 % M] = F[2 % MM]; Fh[2 % M] = F[1]; Fh[3 % M] = F[3 % MM];
     } else {
@@ -307,7 +404,7 @@ constexpr int XS_CELLS = 63;
 // record slots per field and wavefront: the 63 cells and a 2R-cell halo
 __host__ __device__ constexpr int xs_rec(int R) { return (XS_CELLS + 2 * R + 7) / 8 * 8; }
 
-template <int SYS, int M, class T, int MODE, int WV, int R = 3>
+template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0>
 __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>& cfg, int bid) {
   constexpr int XS_REC = xs_rec(R);
   if (a.check_active && !a.ctl->active) return;
@@ -336,7 +433,9 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
     int off[2 * R];
 #pragma unroll
     for (int j = 0; j < 2 * R; ++j) off[j] = lane + j;
-    stencil_flux<SYS, M, 0, T, WV, R>(&xr[wv][0], XS_REC, off, a.ph, a.ctl, cfg.w, F);
+    const double mu = (PP && SYS == SYS_EULER && (MODE == MODE_LX || MODE == MODE_STAGE))
+                          ? pp_mu<0>(a.ctl, a.g, MODE == MODE_LX) : 0.0;
+    stencil_flux<SYS, M, 0, T, WV, R>(&xr[wv][0], XS_REC, off, a.ph, a.ctl, cfg.w, F, mu);
     if (MODE == MODE_FLUX) {
       if (lane < XS_CELLS || k == nx) {
 #pragma unroll
@@ -438,7 +537,7 @@ __device__ __forceinline__ void progress_prio(int st, int nst) {
 // One wavefront's tile: columns x0 .. x0+YS_COLS-1, cell rows [y0, ylast)
 // (interfaces y0 .. ylast).  MODE_STAGE folds the wave speeds of the new
 // states into rs.
-template <int SYS, int M, class T, int MODE, int WV, int R = 3>
+template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0>
 __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>& cfg, int x0, int y0, int ylast,
                                              double (&rs)[NPART]) {
   constexpr int YS_RING = ys_ring(R);
@@ -486,7 +585,8 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
       int off[2 * R];
 #pragma unroll
       for (int j = 0; j < 2 * R; ++j) off[j] = slot(k - R + j) * RS;
-      stencil_flux<SYS, M, 1, T, WV, R>(rw, YS_COLS, off, a.ph, a.ctl, cfg.w, F);
+      const double mu = (PP && SYS == SYS_EULER && MODE == MODE_STAGE) ? pp_mu<1>(a.ctl, a.g, true) : 0.0;
+      stencil_flux<SYS, M, 1, T, WV, R>(rw, YS_COLS, off, a.ph, a.ctl, cfg.w, F, mu);
 #pragma unroll
       for (int c = 0; c < M; ++c) fw[fslot(k)][c][cl] = (double)F[c];
       if (MODE == MODE_FLUX && (k < kend || k == ny)) {
@@ -536,7 +636,7 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
 
 // Block (bx, by) owns 64 columns, one YS_COLS-column tile per wavefront, and
 // band by of the ceil(ny / ytile) bands of (near) equal height.
-template <int SYS, int M, class T, int MODE, int WV, int R = 3>
+template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0>
 __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>& cfg, int bx, int by, int gx) {
   if (a.check_active && !a.ctl->active) return;
   double rs[NPART];
@@ -545,7 +645,7 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
   const int ny = a.g.ny;
   const int nb = (ny + a.ytile - 1) / a.ytile;
   const int y0 = (int)((long long)by * ny / nb), ylast = (int)((long long)(by + 1) * ny / nb);
-  sweep_y_tile<SYS, M, T, MODE, WV, R>(a, cfg, bx * 64 + wave_id() * YS_COLS, y0, ylast, rs);
+  sweep_y_tile<SYS, M, T, MODE, WV, R, PP>(a, cfg, bx * 64 + wave_id() * YS_COLS, y0, ylast, rs);
   if (MODE == MODE_STAGE && a.part)
     block_max_store(rs, a.part + ((size_t)by * gx + bx) * NPART);
 }
@@ -568,6 +668,15 @@ __global__ __launch_bounds__(256, ZA_YS_WAVES) void k_sweep_y(SweepArgs a, CfgAr
 template <int SYS, int M, class T, int MODE, int WV, int R = 3>
 __global__ __launch_bounds__(256) void k_sweep_y_any(SweepArgs a, CfgArg<T> cfg) {
   sweep_y_body<SYS, M, T, MODE, WV, R>(a, cfg, blockIdx.x, blockIdx.y, gridDim.x);
+}
+// Stages with the positivity-preserving limiter (Euler, FP64, r = 3).
+template <int M, int MODE, int WV>
+__global__ __launch_bounds__(256) void k_sweep_x_pp(SweepArgs a, CfgArg<double> cfg) {
+  sweep_x_body<SYS_EULER, M, double, MODE, WV, 3, 1>(a, cfg, blockIdx.x);
+}
+template <int MODE, int WV>
+__global__ __launch_bounds__(256) void k_sweep_y_pp(SweepArgs a, CfgArg<double> cfg) {
+  sweep_y_body<SYS_EULER, 4, double, MODE, WV, 3, 1>(a, cfg, blockIdx.x, blockIdx.y, gridDim.x);
 }
 // Other orders with Z weights: an occupancy target per stencil width.
 template <int SYS, int M, class T, int MODE, int WV, int R, int WAVES>

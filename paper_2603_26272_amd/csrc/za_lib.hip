@@ -56,6 +56,18 @@ za_status za_validate(const za_problem* p, std::string* why) {
   if (p->precision == ZA_FP32_RECON && (p->eps < 1e-37 || (p->affine_invariant && p->mu0 < 1e-18)))
     return fail("FP32 reconstruction needs eps >= 1e-37 and mu0 >= 1e-18 (normal FP32 range)");
   if (p->order != 0 && (p->order < 2 || p->order > 5)) return fail("order r must be 2, 3, 4 or 5");
+  if (p->pp_limiter != 0 && p->pp_limiter != 1) return fail("pp_limiter must be 0 or 1");
+  if (p->pp_limiter && p->system != ZA_EULER) return fail("the positivity limiter applies to the Euler equations");
+  if (p->pp_limiter && (p->dt_rule != ZA_DT_CFL || p->cfl > 0.5))
+    return fail("the positivity limiter needs the CFL time step with cfl <= 0.5");
+  if (p->pp_limiter && order_of(*p) != 3) {
+    if (why) *why = "the positivity limiter runs with r = 3 only";
+    return ZA_ERR_UNSUPPORTED;
+  }
+  if (p->pp_limiter && p->precision != ZA_FP64) {
+    if (why) *why = "the positivity limiter runs with FP64 reconstruction only";
+    return ZA_ERR_UNSUPPORTED;
+  }
   if (order_of(*p) != 3 && p->precision != ZA_FP64) {
     if (why) *why = "orders other than r = 3 run in FP64 only";
     return ZA_ERR_UNSUPPORTED;
@@ -125,6 +137,15 @@ static void launch_x_t(za_ctx* c, int mode, const SweepArgs& a) {
   const int nseg = (a.g.nx + XS_CELLS - 1) / XS_CELLS;
   const long long waves = (long long)a.g.ny * nseg;
   const dim3 grid((unsigned)((waves + 3) / 4)), blk(256);
+  if constexpr (SYS == SYS_EULER && sizeof(T) == sizeof(double)) {
+    if (c->ph.pp && (mode == MODE_LX || mode == MODE_STAGE)) {
+      if (mode == MODE_LX)
+        hipLaunchKernelGGL((k_sweep_x_pp<M, MODE_LX, WV>), grid, blk, 0, c->stream, a, cfg);
+      else
+        hipLaunchKernelGGL((k_sweep_x_pp<M, MODE_STAGE, WV>), grid, blk, 0, c->stream, a, cfg);
+      return;
+    }
+  }
   if constexpr (WV == WV_Z1) {
     switch (mode) {
       case MODE_FLUX: hipLaunchKernelGGL((k_sweep_x_any<SYS, M, T, MODE_FLUX, WV>), grid, blk, 0, c->stream, a, cfg); break;
@@ -146,6 +167,12 @@ template <int SYS, int M, class T, int WV>
 static void launch_y_t(za_ctx* c, int mode, const SweepArgs& a) {
   const CfgArg<T> cfg = make_cfg<T>(c->prob);
   const dim3 grid((unsigned)((a.g.nx + 63) / 64), (unsigned)((a.g.ny + a.ytile - 1) / a.ytile)), blk(256);
+  if constexpr (SYS == SYS_EULER && M == 4 && sizeof(T) == sizeof(double)) {
+    if (c->ph.pp && mode == MODE_STAGE) {
+      hipLaunchKernelGGL((k_sweep_y_pp<MODE_STAGE, WV>), grid, blk, 0, c->stream, a, cfg);
+      return;
+    }
+  }
   if constexpr (WV == WV_Z1) {
     switch (mode) {
       case MODE_FLUX: hipLaunchKernelGGL((k_sweep_y_any<SYS, M, T, MODE_FLUX, WV>), grid, blk, 0, c->stream, a, cfg); break;
@@ -437,6 +464,7 @@ za_status za_ctx_create(const za_problem* p, void* stream, za_ctx** out) {
   c->ph.cfl = p->cfl;
   c->ph.dt_rule = p->dt_rule;
   c->ph.lf_scalar = p->lf == ZA_LF_SCALAR ? 1 : 0;
+  c->ph.pp = p->pp_limiter ? 1 : 0;
   c->red_blocks = (int)std::min<size_t>(RED_BLOCKS_MAX, std::max<size_t>(1, (ncell + 2047) / 2048));
   c->ytile = p->precision == ZA_FP32_RECON ? pick_ytile<float>(c) : pick_ytile<double>(c);
   if (p->dim == 2) {

@@ -363,6 +363,7 @@ static void admit(za_server* sv) {
     d.ph.gamma = p.gamma; d.ph.gm1 = p.gamma - 1.0;
     d.ph.adv[0] = p.adv_speed[0]; d.ph.adv[1] = p.adv_speed[1];
     d.ph.cfl = p.cfl; d.ph.dt_rule = p.dt_rule; d.ph.lf_scalar = p.lf == ZA_LF_SCALAR ? 1 : 0;
+    d.ph.pp = 0;   // requests with the limiter are not admitted
     d.eps16 = 16.0 * p.eps; d.eps4 = 4.0 * p.eps; d.mu0x2 = 2.0 * p.mu0;
     d.xblocks = xb; d.ystrips = ys; d.yblocks = yb; d.stage_blocks = sb;
     // upload, control block, and the wave speeds of Q^0
@@ -491,9 +492,13 @@ za_status za_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t d
 za_status za_server_submit(za_server* sv, const za_problem* p, const double* q0, int64_t n_steps, za_req_id* id) {
   if (!sv || !p || !q0 || !id || n_steps < 1) return ZA_ERR_ARG;
   std::string why;
-  if (za_validate(p, &why) != ZA_OK) return ZA_ERR_ARG;
+  {
+    const za_status vs = za_validate(p, &why);
+    if (vs != ZA_OK) return vs;
+  }
   // batches run the paper's weights (Z type, p = 1, mu = 1) on the Euler equations
-  if (p->system != ZA_EULER || p->p != 1.0 || p->affine_invariant || p->linear_weights || order_of(*p) != 3)
+  if (p->system != ZA_EULER || p->p != 1.0 || p->affine_invariant || p->linear_weights || order_of(*p) != 3 ||
+      p->pp_limiter)
     return ZA_ERR_UNSUPPORTED;
   int sb, xb, ys, yb;
   if (footprint(*p, &sb, &xb, &ys, &yb) > sv->budget) return ZA_ERR_NOMEM;

@@ -44,6 +44,7 @@ class Problem:
     lf: int = LF_PER_FIELD
     linear_weights: int = 0
     order: int = 3          # r of the order-2r central-upwind scheme (3: WENO-ZA6)
+    pp_limiter: int = 0     # 1: positivity-preserving flux limiter in time steps (Euler, FP64)
 
     @property
     def m(self) -> int:

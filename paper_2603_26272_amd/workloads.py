@@ -23,6 +23,8 @@ data, and these generators stand in for them):
                            T = 20 on periodic [-1, 1]).
   * ``burgers_sine``     - Burgers u0 = 1/2 + sin(2 pi x) (tab:scalar_fluxes).
   * ``buckley_step``     - Buckley-Leverett step data (tab:scalar_fluxes).
+  * ``vacuum_tube``, ``leblanc``, ``vacuum_quadrants_2d`` - near-vacuum
+                           Euler data for the positivity-preserving limiter.
   * ``serving_stream``   - a Poisson stream of mixed 1D / 2D solve requests.
 """
 import math
@@ -326,3 +328,45 @@ def buckley_step(N: int = 200) -> Tuple[Problem, np.ndarray]:
     P = Problem(dim=1, system=BUCKLEY, nx=N, ny=1, xlo=-1.0, xhi=1.0, bc_x=TRANSMISSIVE, cfl=0.45)
     x = centres(N, -1.0, 1.0)
     return P, np.where((x >= -0.5) & (x <= 0.0), 1.0, 0.0).reshape(1, 1, N)
+
+
+# --------------------------------------------------------------------------
+# Near-vacuum Euler data (positivity-preserving limiter).
+def _tube(left, right, N, lo, hi, x0, gamma, periodic=False):
+    x = centres(N, lo, hi)
+    L = x < x0
+    if periodic:
+        # the right state also fills the first quarter: two opposite jumps
+        L = L & (x >= lo + 0.5 * (x0 - lo))
+    q = conservative(np.where(L, left[0], right[0]), np.where(L, left[1], right[1]), 0.0,
+                     np.where(L, left[2], right[2]), gamma=gamma, dim=1)
+    P = Problem(dim=1, system=EULER, nx=N, ny=1, xlo=lo, xhi=hi, bc_x=PERIODIC if periodic else TRANSMISSIVE,
+                cfl=0.45, gamma=gamma)
+    return P, q.reshape(3, 1, N)
+
+
+def vacuum_tube(N: int = 200, speed: float = 8.0, periodic: bool = False):
+    """Double rarefaction rho = 1, p = 0.4, u = -speed | +speed at x = 0 on
+    [-5, 5] (T = 0.6): for speed > 3.74 the exact solution contains vacuum.
+    periodic: the domain wraps and a second, colliding jump sits at x = -2.5."""
+    return _tube((1.0, -speed, 0.4), (1.0, speed, 0.4), N, -5.0, 5.0, 0.0, 1.4, periodic), 0.6
+
+
+def leblanc(N: int = 400):
+    """Leblanc's shock tube: gamma = 5/3, (rho, u, p) = (1, 0, 2/3 10^-1) |
+    (10^-3, 0, 2/3 10^-10) at x = 3 on [0, 9], T = 6."""
+    g = 5.0 / 3.0
+    return _tube((1.0, 0.0, (g - 1.0) * 1e-1), (1e-3, 0.0, (g - 1.0) * 1e-10), N, 0.0, 9.0, 3.0, g), 6.0
+
+
+def vacuum_quadrants_2d(n: int = 64, speed: float = 6.0):
+    """Four quadrants rho = 1, p = 0.4 moving apart from the centre of
+    [0, 1]^2 (velocities (+-speed, +-speed)), transmissive; near vacuum
+    forms at the centre."""
+    x = centres(n, 0.0, 1.0)[None, :]
+    y = centres(n, 0.0, 1.0)[:, None]
+    u = np.where(x > 0.5, speed, -speed) * np.ones_like(y)
+    v = np.where(y > 0.5, speed, -speed) * np.ones_like(x)
+    q = conservative(np.ones((n, n)), u, v, np.full((n, n), 0.4), dim=2)
+    P = Problem(dim=2, system=EULER, nx=n, ny=n, bc_x=TRANSMISSIVE, bc_y=TRANSMISSIVE, cfl=0.45)
+    return P, np.ascontiguousarray(q)

@@ -44,6 +44,7 @@ class ZaProblem(C.Structure):
         ("lf", C.c_int32),
         ("linear_weights", C.c_int32),
         ("order", C.c_int32),
+        ("pp_limiter", C.c_int32),
     ]
 
     @classmethod
