@@ -416,6 +416,42 @@ def study_scalar(torch, Context):
     return out
 
 
+def study_pp(torch, Context, n=2048, steps=20):
+    """Cost and reach of the positivity-preserving limiter: the 2D Euler
+    workload (2048^2, 20 steps) with and without it (every face evaluates
+    its half states; few are limited), and the near-vacuum diverging
+    quadrants at 1024^2 to T = 0.05, which fail without it."""
+    import numpy as np
+
+    from paper_2603_26272_amd import workloads as W
+    from paper_2603_26272_amd.za import ZA_OK
+    out = {"study": "positivity-preserving limiter (2D Euler FP64)", "runs": []}
+    P, q0 = W.quadrants_2d(0, n)
+    ir_step = 3 * ir_per_rhs(n, n)
+    for pp in (0, 1):
+        _, wall, info, avg_ms, counts = run_gpu(P.with_(pp_limiter=pp, cfl=0.45), q0, steps, 2, torch, Context)
+        out["runs"].append({"workload": f"quadrants {n}x{n} CFL 0.45", "pp_limiter": pp, "IR_s": ir_step * steps / wall,
+                            "ms_per_step": wall / steps * 1e3, "x_ms": avg_ms[0], "y_ms": avg_ms[1]})
+    m = 1024
+    Pv, qv = W.vacuum_quadrants_2d(m)
+    for pp in (0, 1):
+        q = torch.from_numpy(qv).to("cuda")
+        with Context(Pv.with_(pp_limiter=pp)) as ctx:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = ctx.solve(q, 0.05, check=False)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        rho = q[0]
+        pr = 0.4 * (q[3] - 0.5 * (q[1] ** 2 + q[2] ** 2) / rho)
+        out["runs"].append({"workload": f"vacuum quadrants {m}x{m} to T = 0.05", "pp_limiter": pp,
+                            "status": res["status"], "ok": res["status"] == ZA_OK, "steps": res["steps"],
+                            "t": res["t"], "wall_s": wall,
+                            "rho_min": float(rho.min()) if res["status"] == ZA_OK else None,
+                            "p_min": float(pr.min()) if res["status"] == ZA_OK else None})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -431,7 +467,7 @@ def main():
                     help="Poisson rates (req/s) of the serving leg; the full sweep is 10,25,50,100,200")
     ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--serving-budget-gb", type=float, default=4.0)
-    ap.add_argument("--study", choices=["c0", "c1", "c3", "orders", "scalar", "serving"], default=None,
+    ap.add_argument("--study", choices=["c0", "c1", "c3", "orders", "scalar", "pp", "serving"], default=None,
                     help="run one workload study instead of the benchmark line")
     args = ap.parse_args()
 
@@ -458,6 +494,8 @@ def main():
             res = study_orders(torch, Context)
         elif args.study == "scalar":
             res = study_scalar(torch, Context)
+        elif args.study == "pp":
+            res = study_pp(torch, Context)
         else:
             rates = [float(x) for x in args.serving_rates.split(",") if x]
             res = {"study": "serving sweep", "hbm_budget_gb": args.serving_budget_gb,
