@@ -452,6 +452,30 @@ def study_pp(torch, Context, n=2048, steps=20):
     return out
 
 
+def study_adr(torch, Context, n=256):
+    """Approximate dispersion relation (Section 3.2) of CT6, WENO-ZA6 with tau
+    and with tau', and the other even orders: Phi(phi) of every resolvable
+    mode of an n-cell periodic grid from libza's right-hand side, at three
+    amplitudes (the Z weights are scale-invariant up to epsilon)."""
+    import numpy as np
+
+    from paper_2603_26272_amd import adr
+    out = {"study": f"approximate dispersion relation, N = {n}", "schemes": {}}
+    for name, kw in adr.SCHEMES.items():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi, Phi = adr.adr_gpu(n, **kw)
+        wall = time.perf_counter() - t0
+        amp = max(float(np.abs(adr.adr_gpu(n, amplitude=a, **kw)[1] - Phi).max()) for a in (1e-3, 1e3))
+        k = int(np.argmax(Phi.imag))
+        pick = [int(np.argmin(np.abs(phi - v))) for v in (0.25, 0.5, 0.7, 1.0, 1.5, 2.0, 2.5, 3.0, np.pi)]
+        out["schemes"][name] = {"wall_s": wall, "max_im": float(Phi.imag[k]), "phi_at_max_im": float(phi[k]),
+                                "max_abs_phi_error_below_0.5": float(np.abs(Phi - phi)[phi < 0.5].max()),
+                                "amplitude_dependence": amp,
+                                "samples": [[float(phi[i]), float(Phi[i].real), float(Phi[i].imag)] for i in pick]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -467,7 +491,7 @@ def main():
                     help="Poisson rates (req/s) of the serving leg; the full sweep is 10,25,50,100,200")
     ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--serving-budget-gb", type=float, default=4.0)
-    ap.add_argument("--study", choices=["c0", "c1", "c3", "orders", "scalar", "pp", "serving"], default=None,
+    ap.add_argument("--study", choices=["c0", "c1", "c3", "orders", "scalar", "pp", "adr", "serving"], default=None,
                     help="run one workload study instead of the benchmark line")
     args = ap.parse_args()
 
@@ -496,6 +520,8 @@ def main():
             res = study_scalar(torch, Context)
         elif args.study == "pp":
             res = study_pp(torch, Context)
+        elif args.study == "adr":
+            res = study_adr(torch, Context)
         else:
             rates = [float(x) for x in args.serving_rates.split(",") if x]
             res = {"study": "serving sweep", "hbm_budget_gb": args.serving_budget_gb,

@@ -94,6 +94,10 @@ typedef struct {
                            /* pressure stay >= 1e-13 (Hu, Adams and Shu 2013, */
                            /* cited in Section 4.3; needs cfl <= 0.5); the    */
                            /* right-hand-side calls are not limited           */
+  int32_t alt_tau;         /* 1: the alternative global indicator tau' =      */
+                           /* (13/12) <c_tau,f>^2 + <c'_tau,f>^2 of eq:GSI_alt */
+                           /* (r = 3; for the dispersion analysis, Section    */
+                           /* 3.2); 0: tau of eq:GSI                           */
 } za_problem;
 
 typedef struct za_ctx za_ctx;

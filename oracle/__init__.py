@@ -41,6 +41,7 @@ class _Problem(C.Structure):
         ("linear_weights", C.c_int32),
         ("order", C.c_int32),
         ("pp_limiter", C.c_int32),
+        ("alt_tau", C.c_int32),
     ]
 
 
@@ -56,6 +57,8 @@ def lib():
         L = C.CDLL(_LIB_PATH)
         L.orc_recon.restype = C.c_double
         L.orc_recon.argtypes = [_DP, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int, _DP]
+        L.orc_recon_alt.restype = C.c_double
+        L.orc_recon_alt.argtypes = [_DP, C.c_double, C.c_double, C.c_int, C.c_double, _DP]
         L.orc_recon_f32.restype = C.c_double
         L.orc_recon_f32.argtypes = [_DP, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int]
         L.orc_recon_q.restype = C.c_double
@@ -128,6 +131,7 @@ def _problem(pb) -> _Problem:
     P.linear_weights = int(_get(pb, "linear_weights", 0))
     P.order = int(_get(pb, "order", 3))
     P.pp_limiter = int(_get(pb, "pp_limiter", 0))
+    P.alt_tau = int(_get(pb, "alt_tau", 0))
     _ensure_order(P.order)
     return P
 
@@ -191,6 +195,18 @@ def recon_r(r, v, p=1.0, eps=1e-40, ai=0, mu0=1e-40, linear=0, prec=0, detail=Fa
                      "beta_r": d[2 * r + 2], "tau": d[2 * r + 3], "mu": d[2 * r + 4],
                      "omega": d[2 * r + 5:3 * r + 6].copy()}
     return lib().orc_recon_r(int(r), _ptr(v), p, eps, ai, mu0, linear, prec, None)
+
+
+def recon_alt(v6, p=1.0, eps=1e-40, ai=0, mu0=1e-40, detail=False):
+    """O1 with the alternative global indicator tau' (eq:GSI_alt)."""
+    v = np.ascontiguousarray(v6, dtype=np.float64)
+    assert v.shape == (6,)
+    if detail:
+        d = np.zeros(15)
+        r = lib().orc_recon_alt(_ptr(v), p, eps, ai, mu0, _ptr(d))
+        return r, {"q": d[0:4].copy(), "beta": d[4:9].copy(), "tau": d[9], "mu": d[10],
+                   "omega": d[11:15].copy()}
+    return lib().orc_recon_alt(_ptr(v), p, eps, ai, mu0, None)
 
 
 def recon_f32(v6, p=1.0, eps=1e-20, ai=0, mu0=1e-8, linear=0):

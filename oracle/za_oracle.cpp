@@ -132,6 +132,7 @@ struct ReconParams {
   int ai;          /* 1: affine-invariant descaler mu[f] of eq:aimu       */
   double mu0;      /* mu_0 of eq:aimu                                      */
   int linear;      /* 1: omega = d (the linear sixth-order central flux)   */
+  int alt_tau = 0; /* 1: the alternative indicator tau' of eq:GSI_alt      */
 };
 
 /* Constants of the r = 3 scheme, built in the arithmetic type R so that the
@@ -214,10 +215,18 @@ static R recon_za6(const R v[6], const ZA6Const<R>& K, const ReconParams& P,
   R beta3 = K.quarter * (beta[0] + beta[1] + beta[2] + beta_d);
   R b[4] = {beta[0], beta[1], beta[2], beta3};
 
-  /* Global smoothness indicator tau = <c_tau, f^6>^2 (eq:GSI). */
+  /* Global smoothness indicator tau = <c_tau, f^6>^2 (eq:GSI), or the
+   * alternative tau' = (13/12) <c_tau, f^6>^2 + <c'_tau, f^6>^2 with
+   * c'_tau = (1, -4, 6, -4, 1, 0) (eq:GSI_alt, the remark after eq:GSI). */
   R t = R(0);
   for (int j = 0; j < 6; ++j) t = t + K.ctau[j] * v[j];
   R tau = t * t;
+  if (P.alt_tau) {
+    const int ctp[6] = {1, -4, 6, -4, 1, 0};
+    R t4 = R(0);
+    for (int j = 0; j < 6; ++j) t4 = t4 + lit<R>((double)ctp[j]) * v[j];
+    tau = frac<R>(13, 12) * tau + t4 * t4;
+  }
 
   /* Descaler mu[f] (eq:aimu); mu = 1 for the non-Ai Z weights. */
   R mu = R(1);
@@ -425,6 +434,7 @@ typedef struct {
   int32_t linear_weights;
   int32_t order;          /* r of the order-2r scheme (0 or 3: WENO-ZA6) */
   int32_t pp_limiter;     /* 1: positivity-preserving flux limiter in steps */
+  int32_t alt_tau;        /* 1: tau' of eq:GSI_alt instead of tau (r = 3)   */
 } orc_problem;
 }
 
@@ -730,6 +740,8 @@ static int make_ctx(const orc_problem* p, Ctx* C) {
   if (C->r != 3 && !g_gen[C->r].set) return 1;   /* tables not handed over */
   C->RP.p = p->p; C->RP.eps = p->eps; C->RP.ai = p->ai; C->RP.mu0 = p->mu0;
   C->RP.linear = p->linear_weights;
+  C->RP.alt_tau = p->alt_tau;
+  if (p->alt_tau && C->r != 3) return 1;
   C->dx = (p->xhi - p->xlo) / p->nx;
   C->dy = p->dim == 2 ? (p->yhi - p->ylo) / p->ny : 1.0;
   C->ncell = (size_t)p->nx * p->ny;
@@ -987,6 +999,16 @@ int orc_get_threads(void) {
 double orc_recon(const double* v6, double p, double eps, int ai, double mu0, int linear, double* detail) {
   static const ZA6Const<double> K;
   ReconParams RP{p, eps, ai, mu0, linear};
+  ReconDetail d;
+  double r = recon_za6<double>(v6, K, RP, detail ? &d : nullptr);
+  if (detail) std::memcpy(detail, &d, sizeof(d));
+  return r;
+}
+/* As orc_recon with the alternative global indicator tau' (eq:GSI_alt). */
+double orc_recon_alt(const double* v6, double p, double eps, int ai, double mu0, double* detail) {
+  static const ZA6Const<double> K;
+  ReconParams RP{p, eps, ai, mu0, 0};
+  RP.alt_tau = 1;
   ReconDetail d;
   double r = recon_za6<double>(v6, K, RP, detail ? &d : nullptr);
   if (detail) std::memcpy(detail, &d, sizeof(d));

@@ -30,6 +30,7 @@ struct WeightCfg {
   T p;        // power parameter (1 on the fast path)
   int ai;     // 1: affine-invariant descaler
   int linear; // 1: omega = d
+  int alt_tau; // 1: tau' of eq:GSI_alt (r = 3, general weights)
 };
 
 // Weight variants compiled as separate kernels: the paper's Z weights with
@@ -159,6 +160,12 @@ __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const Weigh
   const T Bd = fma(k133 * e3, e3, g3 * g3);
   T B3 = T(0.25) * ((B0 + B1) + (B2 + Bd));
   T tau = t2 * t2;
+  if (WV == WV_GENERAL && w.alt_tau) {
+    // tau' = (13/12) <c_tau, f>^2 + <c'_tau, f>^2, c'_tau = (1,-4,6,-4,1,0):
+    // with s = 2f, 16 tau' = (13/12) t2^2 + (2 (e0 - 2 e1 + e2))^2
+    const T t4 = fma(T(-2), e1, e0 + e2);
+    tau = fma(T(13.0 / 12.0), tau, T(4) * (t4 * t4));
+  }
   T eps = w.eps16;
   if (WV == WV_GENERAL && w.ai) {
     const T mean = (s0 + s1 + s2 + s3 + s4 + s5) * c16;

@@ -42,6 +42,12 @@ za_status za_validate(const za_problem* p, std::string* why);
 // r of the order-2r scheme (0 selects WENO-ZA6, r = 3)
 inline int order_of(const za_problem& p) { return p.order == 0 ? 3 : p.order; }
 
+// Z weights with p = 1 and mu = 1 take the fast kernels; Ai, p != 1, tau'
+// and the linear-weight test mode take the general ones.
+inline bool general_weights(const za_problem& p) {
+  return p.p != 1.0 || p.affine_invariant || p.linear_weights || p.alt_tau;
+}
+
 template <class T>
 inline za::CfgArg<T> make_cfg(const za_problem& p) {
   za::CfgArg<T> c;
@@ -53,6 +59,7 @@ inline za::CfgArg<T> make_cfg(const za_problem& p) {
   c.w.p = (T)p.p;
   c.w.ai = p.affine_invariant;
   c.w.linear = p.linear_weights;
+  c.w.alt_tau = p.alt_tau;
   return c;
 }
 

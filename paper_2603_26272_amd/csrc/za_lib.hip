@@ -57,6 +57,11 @@ za_status za_validate(const za_problem* p, std::string* why) {
     return fail("FP32 reconstruction needs eps >= 1e-37 and mu0 >= 1e-18 (normal FP32 range)");
   if (p->order != 0 && (p->order < 2 || p->order > 5)) return fail("order r must be 2, 3, 4 or 5");
   if (p->pp_limiter != 0 && p->pp_limiter != 1) return fail("pp_limiter must be 0 or 1");
+  if (p->alt_tau != 0 && p->alt_tau != 1) return fail("alt_tau must be 0 or 1");
+  if (p->alt_tau && order_of(*p) != 3) {
+    if (why) *why = "the alternative global indicator is defined here for r = 3 only";
+    return ZA_ERR_UNSUPPORTED;
+  }
   if (p->pp_limiter && p->system != ZA_EULER) return fail("the positivity limiter applies to the Euler equations");
   if (p->pp_limiter && (p->dt_rule != ZA_DT_CFL || p->cfl > 0.5))
     return fail("the positivity limiter needs the CFL time step with cfl <= 0.5");
@@ -188,11 +193,6 @@ static void launch_y_t(za_ctx* c, int mode, const SweepArgs& a) {
   }
 }
 
-// Z weights with p = 1 and mu = 1 take the fast kernels; Ai, p != 1 and the
-// linear-weight test mode take the general ones.
-static bool general_weights(const za_problem& p) {
-  return p.p != 1.0 || p.affine_invariant || p.linear_weights;
-}
 
 // dispatch on (system, dim, precision, weight variant)
 template <int SYS, int M>

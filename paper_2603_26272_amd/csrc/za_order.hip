@@ -17,7 +17,6 @@ template <> struct OrderWaves<5> { enum { x = 2, y = 2 }; };
 
 // Z weights with p = 1 take the occupancy-targeted kernels; Ai, p != 1 and
 // linear weights the general ones.
-bool general_weights(const za_problem& p) { return p.p != 1.0 || p.affine_invariant || p.linear_weights; }
 
 template <int SYS, int M, int R>
 void x_sys(za_ctx* c, int mode, const SweepArgs& a) {

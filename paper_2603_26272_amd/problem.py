@@ -45,6 +45,7 @@ class Problem:
     linear_weights: int = 0
     order: int = 3          # r of the order-2r central-upwind scheme (3: WENO-ZA6)
     pp_limiter: int = 0     # 1: positivity-preserving flux limiter in time steps (Euler, FP64)
+    alt_tau: int = 0        # 1: the alternative global indicator tau' (eq:GSI_alt; r = 3)
 
     @property
     def m(self) -> int:

@@ -45,6 +45,7 @@ class ZaProblem(C.Structure):
         ("linear_weights", C.c_int32),
         ("order", C.c_int32),
         ("pp_limiter", C.c_int32),
+        ("alt_tau", C.c_int32),
     ]
 
     @classmethod
