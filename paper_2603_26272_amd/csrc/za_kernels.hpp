@@ -105,15 +105,18 @@ __device__ __forceinline__ void cell_speeds(const double (&Q)[M], const Phys& ph
     const double u = mx * ir, v = my * ir;
     const double p = ph.gm1 * fma(-0.5 * rho, fma(u, u, v * v), E);
     const double c2 = ph.gamma * p * ir;
-    const bool ok = rho > 0.0 && p > 0.0 && c2 > 0.0 && (E - E) == 0.0 && (mx - mx) == 0.0 && (my - my) == 0.0;
+    // A NaN or infinite component makes p NaN, -inf or +inf (then c2 = +inf),
+    // so these tests also reject every non-finite state; past them all
+    // speeds are numbers and fmax needs no NaN care.
+    const bool ok = rho > 0.0 && p > 0.0 && c2 > 0.0 && c2 < __builtin_huge_val();
     if (!ok) { r[0] = __builtin_huge_val(); return; }
     const double c = sqrt_nr(c2);
-    r[0] = wave_max(r[0], fabs(u - c));
-    r[1] = wave_max(r[1], fabs(u));
-    r[2] = wave_max(r[2], fabs(u + c));
-    r[3] = wave_max(r[3], fabs(v - c));
-    r[4] = wave_max(r[4], fabs(v));
-    r[5] = wave_max(r[5], fabs(v + c));
+    r[0] = fmax(r[0], fabs(u - c));
+    r[1] = fmax(r[1], fabs(u));
+    r[2] = fmax(r[2], fabs(u + c));
+    r[3] = fmax(r[3], fabs(v - c));
+    r[4] = fmax(r[4], fabs(v));
+    r[5] = fmax(r[5], fabs(v + c));
   } else if (SYS == SYS_BUCKLEY) {
     // non-convex flux: keep the data range (max u, max -u); the final
     // reduction takes max |f'| over it
@@ -314,40 +317,55 @@ __device__ void pp_limit_face(const double* __restrict__ rec, int fs, int oL, in
   }
 }
 
-// Limiter step size of a sweep in direction DIR for the stage in progress
-// (0: no limiting): mu = dt S / s_DIR.
+// Constants of one sweep launch, read from the control block before the
+// sweep writes anything (so they load once, into scalar registers): the LF
+// speeds of the sweep direction, dt, the direction's max(|u_n| + c) and the
+// limiter step size mu = dt S / s_DIR (0: no limiting).
+struct SweepConst {
+  double al[4];
+  double dt, smax, mu;
+};
+
 template <int DIR>
-__device__ __forceinline__ double pp_mu(const DevCtl* ctl, const Geom& g, bool two_d) {
-  const double sx = ctl->smax[0], sy = two_d ? ctl->smax[1] : 0.0;
-  const double S = fma(sx, g.inv_dx, two_d ? sy * g.inv_dy : 0.0);
-  const double sd = DIR == 0 ? sx : sy;
-  return sd > 0.0 ? ctl->dt * S / sd : 0.0;
+__device__ __forceinline__ SweepConst sweep_const(const DevCtl* ctl, const Geom& g, bool pp, bool two_d) {
+  SweepConst k;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) k.al[s] = ctl->alpha[DIR][s];
+  k.dt = ctl->dt;
+  k.smax = ctl->smax[DIR];
+  k.mu = 0.0;
+  if (pp) {
+    const double sx = ctl->smax[0], sy = two_d ? ctl->smax[1] : 0.0;
+    const double S = fma(sx, g.inv_dx, two_d ? sy * g.inv_dy : 0.0);
+    const double sd = DIR == 0 ? sx : sy;
+    k.mu = sd > 0.0 ? k.dt * S / sd : 0.0;
+  }
+  return k;
 }
 
 // Interface flux from the records of its six-point stencil; the result is
 // returned in the state's own component order.
 template <int SYS, int M, int DIR, class T, int WV, int R = 3>
 __device__ __forceinline__ void stencil_flux(const T* __restrict__ rec, int fs, const int (&off)[2 * R],
-                                             const Phys& ph, const DevCtl* ctl, const WeightCfg<T>& cfg,
-                                             T (&Fh)[M], double pp_mu_dir = 0.0) {
+                                             const Phys& ph, const SweepConst& sk, const WeightCfg<T>& cfg,
+                                             T (&Fh)[M]) {
   if (SYS == SYS_EULER) {
     constexpr int MM = (M == 1 ? 4 : M);
     T al[MM];
     if (MM == 4) {
-      al[0] = (T)ctl->alpha[DIR][0]; al[1] = (T)ctl->alpha[DIR][1];
-      al[2 % MM] = (T)ctl->alpha[DIR][2]; al[3 % MM] = (T)ctl->alpha[DIR][3];
+      al[0] = (T)sk.al[0]; al[1] = (T)sk.al[1];
+      al[2 % MM] = (T)sk.al[2]; al[3 % MM] = (T)sk.al[3];
     } else {
-      al[0] = (T)ctl->alpha[0][0]; al[1] = (T)ctl->alpha[0][1]; al[MM - 1] = (T)ctl->alpha[0][3];
+      al[0] = (T)sk.al[0]; al[1] = (T)sk.al[1]; al[MM - 1] = (T)sk.al[3];
     }
     T F[MM];
     euler_flux<T, MM, WV, R>(rec, fs, off, (T)ph.gm1, al, cfg, F);
     if constexpr (sizeof(T) == sizeof(double)) {
-      if (pp_mu_dir > 0.0) {
+      if (sk.mu > 0.0) {
         double Fd[MM];
 #pragma unroll
         for (int c = 0; c < MM; ++c) Fd[c] = (double)F[c];
-        pp_limit_face<MM>(reinterpret_cast<const double*>(rec), fs, off[R - 1], off[R], ph.gm1, ctl->smax[DIR],
-                          pp_mu_dir, Fd);
+        pp_limit_face<MM>(reinterpret_cast<const double*>(rec), fs, off[R - 1], off[R], ph.gm1, sk.smax, sk.mu, Fd);
 #pragma unroll
         for (int c = 0; c < MM; ++c) F[c] = (T)Fd[c];
       }
@@ -365,7 +383,7 @@ __device__ __forceinline__ void stencil_flux(const T* __restrict__ rec, int fs, 
       w[j] = rec[off[j]];
       g[j] = rec[fs + off[j]];
     }
-    Fh[0] = split_pair<T, WV, R>(w, g, (T)ctl->alpha[DIR][0], cfg);
+    Fh[0] = split_pair<T, WV, R>(w, g, (T)sk.al[0], cfg);
   }
 }
 
@@ -408,6 +426,8 @@ template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0>
 __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>& cfg, int bid) {
   constexpr int XS_REC = xs_rec(R);
   if (a.check_active && !a.ctl->active) return;
+  const SweepConst sk = sweep_const<0>(a.ctl, a.g, PP && SYS == SYS_EULER && (MODE == MODE_LX || MODE == MODE_STAGE),
+                                       MODE == MODE_LX);
   constexpr int NF = NumFields<SYS, M>::value;
   __shared__ T xr[4][NF * XS_REC];
   __shared__ double fl[4][M][64];
@@ -433,9 +453,7 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
     int off[2 * R];
 #pragma unroll
     for (int j = 0; j < 2 * R; ++j) off[j] = lane + j;
-    const double mu = (PP && SYS == SYS_EULER && (MODE == MODE_LX || MODE == MODE_STAGE))
-                          ? pp_mu<0>(a.ctl, a.g, MODE == MODE_LX) : 0.0;
-    stencil_flux<SYS, M, 0, T, WV, R>(&xr[wv][0], XS_REC, off, a.ph, a.ctl, cfg.w, F, mu);
+    stencil_flux<SYS, M, 0, T, WV, R>(&xr[wv][0], XS_REC, off, a.ph, sk, cfg.w, F);
     if (MODE == MODE_FLUX) {
       if (lane < XS_CELLS || k == nx) {
 #pragma unroll
@@ -476,14 +494,17 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
 #pragma unroll
         for (int c = 0; c < M; ++c) qb[c] = 0.0;
       }
-      const double dt = a.ctl->dt;
 #pragma unroll
       for (int c = 0; c < M; ++c) {
         const double L = -(fl[wv][c][lane + 1] - fl[wv][c][lane]) * a.g.inv_dx;
-        a.out[c * cs + idx] = fma(a.ca, qb[c], a.cb * fma(dt, L, qc[c]));
+        a.out[c * cs + idx] = fma(a.ca, qb[c], a.cb * fma(sk.dt, L, qc[c]));
       }
     } else {
-      double qnew[M];
+      double qnew[M], q0[M], qs[M];
+      if (MODE == MODE_STAGE) {   // loads first (see the y-sweep epilogue)
+#pragma unroll
+        for (int c = 0; c < M; ++c) { q0[c] = a.qn[c * cs + idx]; qs[c] = a.q[c * cs + idx]; }
+      }
 #pragma unroll
       for (int c = 0; c < M; ++c) {
         const double L = -(fl[wv][c][lane + 1] - fl[wv][c][lane]) * a.g.inv_dx;
@@ -491,7 +512,7 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
         if (MODE == MODE_RHS) {
           a.out[o] = L;
         } else {  // MODE_STAGE (1D)
-          qnew[c] = fma(a.ca, a.qn[o], a.cb * fma(a.ctl->dt, L, a.q[o]));
+          qnew[c] = fma(a.ca, q0[c], a.cb * fma(sk.dt, L, qs[c]));
           a.out[o] = qnew[c];
         }
       }
@@ -538,8 +559,8 @@ __device__ __forceinline__ void progress_prio(int st, int nst) {
 // (interfaces y0 .. ylast).  MODE_STAGE folds the wave speeds of the new
 // states into rs.
 template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0>
-__device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>& cfg, int x0, int y0, int ylast,
-                                             double (&rs)[NPART]) {
+__device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>& cfg, const SweepConst& sk, int x0,
+                                             int y0, int ylast, double (&rs)[NPART]) {
   constexpr int YS_RING = ys_ring(R);
   constexpr int NF = NumFields<SYS, M>::value;
   constexpr int RS = NF * YS_COLS + 32 / (int)sizeof(T);   // ring row stride, padded by 32 bytes
@@ -555,16 +576,24 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
   const double* col = a.q + (xin ? x : 0);
   T* const rw = &ring[wv][cl];
   double(*const fw)[M][YS_COLS] = fb[wv];
-  auto slot = [&](int r) { return (r - y0 + R) % YS_RING; };     // r >= y0 - R
-  auto fslot = [&](int k) { return (k - y0 + 1) % YS_FSLOT; };   // k >= y0 - 1
+  // Ring slot of cell row r is (r - y0 + R) mod YS_RING; flux slot of
+  // interface k is (k - y0 + 1) mod YS_FSLOT.  Both advance by YS_ROWS per
+  // step, so each lane carries them (scaled) instead of dividing.
   // rows y0-R .. y0+YS_ROWS+R-2 for the first step
   for (int i = g; i < YS_RING; i += YS_ROWS) {
     if (xin) {
       const int r = y0 - R + i;
-      stage_cell<SYS, M, 1, T>(col, cs, (size_t)bc_map(r, ny, a.g.bc_y) * nx, a.ph, rw + slot(r) * RS, YS_COLS);
+      stage_cell<SYS, M, 1, T>(col, cs, (size_t)bc_map(r, ny, a.g.bc_y) * nx, a.ph, rw + i * RS, YS_COLS);
     }
   }
   wave_sync();
+  // sb: slot of row k - R (the stencil's first row, and the slot that row
+  // k0 + YS_ROWS + R - 1 + g takes at the end of the step), times RS;
+  // fk: flux slot of interface k, fkm of k - 1
+  int sb = g * RS;
+  int fk = g + 1, fkm = g;
+  constexpr int RING_RS = YS_RING * RS;
+  const double cbdt = a.cb * sk.dt;
   const int nst = (kend - y0) / YS_ROWS + 1;
   for (int st = 0; st < nst; ++st) {
     progress_prio(st, nst);
@@ -583,12 +612,15 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
     if (act) {
       T F[M];
       int off[2 * R];
+      off[0] = sb;
 #pragma unroll
-      for (int j = 0; j < 2 * R; ++j) off[j] = slot(k - R + j) * RS;
-      const double mu = (PP && SYS == SYS_EULER && MODE == MODE_STAGE) ? pp_mu<1>(a.ctl, a.g, true) : 0.0;
-      stencil_flux<SYS, M, 1, T, WV, R>(rw, YS_COLS, off, a.ph, a.ctl, cfg.w, F, mu);
+      for (int j = 1; j < 2 * R; ++j) {
+        const unsigned t = (unsigned)(sb + j * RS);
+        off[j] = (int)min(t, t - (unsigned)RING_RS);   // t - RING_RS wraps above t when t < RING_RS
+      }
+      stencil_flux<SYS, M, 1, T, WV, R>(rw, YS_COLS, off, a.ph, sk, cfg.w, F);
 #pragma unroll
-      for (int c = 0; c < M; ++c) fw[fslot(k)][c][cl] = (double)F[c];
+      for (int c = 0; c < M; ++c) fw[fk][c][cl] = (double)F[c];
       if (MODE == MODE_FLUX && (k < kend || k == ny)) {
 #pragma unroll
         for (int c = 0; c < M; ++c) a.out[(size_t)c * (ny + 1) * nx + (size_t)k * nx + x] = (double)F[c];
@@ -598,15 +630,19 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
     const int r = k - 1;   // cell row finished by this lane
     if (MODE != MODE_FLUX && act && r >= y0 && r < ylast) {
       const size_t idx = (size_t)r * nx + x;
-      double qnew[M];
+      double lx[M], qnew[M];
+      // every load before the first store: out never overlaps lx, but the
+      // compiler cannot know that and would serialise them
+#pragma unroll
+      for (int c = 0; c < M; ++c) lx[c] = a.lx[c * cs + idx];
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        const double L = -(fw[fslot(k)][c][cl] - fw[fslot(k - 1)][c][cl]) * a.g.inv_dy;
+        const double L = -(fw[fk][c][cl] - fw[fkm][c][cl]) * a.g.inv_dy;
         const size_t o = c * cs + idx;
         if (MODE == MODE_RHS) {
-          a.out[o] = a.lx[o] + L;
+          a.out[o] = lx[c] + L;
         } else {  // MODE_STAGE: the x-sweep left ca Q^n + cb (Q + dt L_x)
-          qnew[c] = fma(a.cb * a.ctl->dt, L, a.lx[o]);
+          qnew[c] = fma(cbdt, L, lx[c]);
           a.out[o] = qnew[c];
         }
       }
@@ -615,7 +651,7 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
     if (need) {
       // row rn takes the slot of row rn - YS_RING = k0 - R + g, which only
       // this step's stencils (above the synchronisation) read
-      T* rec = rw + slot(rn) * RS;
+      T* rec = rw + sb;
       if (SYS == SYS_EULER) {
         double qd[M];
         if (M == 4) { qd[0] = qp[0]; qd[1] = qp[2 % M]; qd[2 % M] = qp[1]; qd[3 % M] = qp[3 % M]; }
@@ -631,6 +667,12 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
       }
     }
     wave_sync();
+    // advance by YS_ROWS rows (YS_ROWS < YS_RING, YS_ROWS < YS_FSLOT)
+    sb += YS_ROWS * RS;
+    sb = (int)min((unsigned)sb, (unsigned)(sb - RING_RS));
+    fkm = fk + YS_ROWS - 1;
+    fkm = fkm >= YS_FSLOT ? fkm - YS_FSLOT : fkm;
+    fk = fkm + 1 == YS_FSLOT ? 0 : fkm + 1;
   }
 }
 
@@ -639,13 +681,14 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
 template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0>
 __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>& cfg, int bx, int by, int gx) {
   if (a.check_active && !a.ctl->active) return;
+  const SweepConst sk = sweep_const<1>(a.ctl, a.g, PP && SYS == SYS_EULER && MODE == MODE_STAGE, true);
   double rs[NPART];
 #pragma unroll
   for (int t = 0; t < NPART; ++t) rs[t] = -__builtin_huge_val();
   const int ny = a.g.ny;
   const int nb = (ny + a.ytile - 1) / a.ytile;
   const int y0 = (int)((long long)by * ny / nb), ylast = (int)((long long)(by + 1) * ny / nb);
-  sweep_y_tile<SYS, M, T, MODE, WV, R, PP>(a, cfg, bx * 64 + wave_id() * YS_COLS, y0, ylast, rs);
+  sweep_y_tile<SYS, M, T, MODE, WV, R, PP>(a, cfg, sk, bx * 64 + wave_id() * YS_COLS, y0, ylast, rs);
   if (MODE == MODE_STAGE && a.part)
     block_max_store(rs, a.part + ((size_t)by * gx + bx) * NPART);
 }
