@@ -109,6 +109,7 @@ __device__ __forceinline__ float div_nr(float a, float x) { return a * __builtin
 // FP64 fast path: the weights are evaluated over a common denominator,
 //   2f = sum_k d_k (b_k + T) P_k q_k / sum_k d_k (b_k + T) P_k,
 //   b_k = B_k + 16 eps, P_k = prod_{j != k} b_j  (the 1/20 cancels),
+//   (b_k + T) P_k = P + T P_k with P = prod_j b_j,
 // algebraically identical to the normalised weights with one division
 // instead of five.  b_k >= 1.6e-39 keeps every product above 1e-156, so
 // nothing underflows; the products overflow only for flux values beyond
@@ -147,11 +148,13 @@ __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const Weigh
     const T bd = fma(k133 * e3, e3, fma(g3, g3, w.eps16));
     const T b3 = T(0.25) * ((b0 + b1) + (b2 + bd));
     const T tau = t2 * t2;
+    // (b_k + T) P_k = P + T P_k with P = b0 b1 b2 b3
     const T p01 = b0 * b1, p23 = b2 * b3;
-    const T w0 = (b0 + tau) * (b1 * p23);
-    const T v1 = (b1 + tau) * (b0 * p23);   // w_1 / 9
-    const T v2 = (b2 + tau) * (p01 * b3);   // w_2 / 9
-    const T w3 = (b3 + tau) * (p01 * b2);
+    const T P = p01 * p23;
+    const T w0 = fma(tau, b1 * p23, P);
+    const T v1 = fma(tau, b0 * p23, P);   // w_1 / 9
+    const T v2 = fma(tau, p01 * b3, P);   // w_2 / 9
+    const T w3 = fma(tau, p01 * b2, P);
     return div_nr(fma(w0, q0, fma(T(9), fma(v1, q1, v2 * q2), w3 * q3)), fma(T(9), v1 + v2, w0 + w3));
   }
   T B0 = fma(k133 * e0, e0, g0 * g0);
@@ -394,9 +397,15 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
   const T c = sqrt_nr(c2);
   const T ic = rcp_nr(c);
   const T b1 = gm1 * (ic * ic);
-  const T hb1 = T(0.5) * b1, hb2 = hb1 * q2;
-  const T hic = T(0.5) * ic;
-  // project the stencil onto the characteristic fields
+  const T k1 = gm1 * ic;
+  // project the stencil onto the characteristic fields.  With
+  // P = q2 Q0 - (u Q1 + v Q2 - E) and D = u Q0 - Q1 the left eigenvectors
+  // give w_0 = (b1/2) P + D/(2c), w_3 = (b1/2) P - D/(2c), w_1 = Q0 - b1 P;
+  // the acoustic fields 0 and M-1 are carried scaled by 2c, as
+  // (gm1/c) P +- D.  The reconstruction commutes with a constant scale of a
+  // field (its weights are scale-invariant; epsilon aside, which only
+  // matters where a field is flat to 1e-20), so the factor 1/(2c) is
+  // applied to the reconstructed fluxes instead: one FMA per value here.
   T W[M][2 * R], G[M][2 * R];
 #pragma unroll
   for (int j = 0; j < 2 * R; ++j) {
@@ -407,40 +416,41 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
     {
       T K = fma(u, Q1, -E);
       if (M == 4) K = fma(v, Q2, K);
-      const T A = fma(hb2, Q0, -hb1 * K);
-      const T B = hic * fma(u, Q0, -Q1);
-      W[0][j] = A + B;
-      W[1][j] = fma(T(-2), A, Q0);
+      const T P = fma(q2, Q0, -K);
+      const T D = fma(u, Q0, -Q1);
+      W[0][j] = fma(k1, P, D);
+      W[1][j] = fma(-b1, P, Q0);
       if (M == 4) W[2][j] = fma(-v, Q0, Q2);
-      W[M - 1][j] = A - B;
+      W[M - 1][j] = fma(k1, P, -D);
     }
     {
       // physical flux (F0 = Q1, F1, [F2], F3)
       T K = fma(u, F1, -F3);
       if (M == 4) K = fma(v, F2, K);
-      const T A = fma(hb2, Q1, -hb1 * K);
-      const T B = hic * fma(u, Q1, -F1);
-      G[0][j] = A + B;
-      G[1][j] = fma(T(-2), A, Q1);
+      const T P = fma(q2, Q1, -K);
+      const T D = fma(u, Q1, -F1);
+      G[0][j] = fma(k1, P, D);
+      G[1][j] = fma(-b1, P, Q1);
       if (M == 4) G[2][j] = fma(-v, Q1, F2);
-      G[M - 1][j] = A - B;
+      G[M - 1][j] = fma(k1, P, -D);
     }
   }
 #undef ZA_R
   T gh[M];
 #pragma unroll
   for (int s = 0; s < M; ++s) gh[s] = split_pair<T, WV, R>(W[s], G[s], alpha[s], cfg);
-  // back-projection F = R g
-  const T s03 = gh[0] + gh[M - 1], d30 = gh[M - 1] - gh[0];
+  // back-projection F = R g, the acoustic fluxes unscaled by 1/(2c):
+  // gh_0 + gh_3 = (gh'_0 + gh'_3)/(2c), c (gh_3 - gh_0) = (gh'_3 - gh'_0)/2
+  const T s03 = (gh[0] + gh[M - 1]) * (T(0.5) * ic);
+  const T d30 = T(0.5) * (gh[M - 1] - gh[0]);
   const T sum = s03 + gh[1];
-  const T uc = u * c;
   Fh[0] = sum;
-  Fh[1] = fma(u, sum, c * d30);
+  Fh[1] = fma(u, sum, d30);
   if (M == 4) {
     Fh[2] = fma(v, sum, gh[2]);
-    Fh[3] = fma(H, s03, fma(uc, d30, fma(q2, gh[1], v * gh[2])));
+    Fh[3] = fma(H, s03, fma(u, d30, fma(q2, gh[1], v * gh[2])));
   } else {
-    Fh[2] = fma(H, s03, fma(uc, d30, q2 * gh[1]));
+    Fh[2] = fma(H, s03, fma(u, d30, q2 * gh[1]));
   }
 }
 
