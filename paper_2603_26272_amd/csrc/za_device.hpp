@@ -375,7 +375,9 @@ __device__ __forceinline__ void roe_side(const T* __restrict__ rec, int fs, int 
 //                                  (0, 0, 1, v), (1, u+c, v, H+uc)
 //   L rows: A+B, Q0-2A, Q2-vQ0, A-B  with  A = (b2 Q0 - b1 K)/2,
 //   B = (u Q0 - Q1)/(2c), K = u Q1 + v Q2 - E, b1 = (gamma-1)/c^2,
-//   b2 = b1 q2  (the textbook left eigenvectors, factored).
+//   b2 = b1 q2  (the textbook left eigenvectors, factored; the rows A+B and
+//   A-B are applied multiplied by 2c and the matching columns of R divided
+//   by it, which leaves F = R WENO(L f) unchanged).
 // ---------------------------------------------------------------------------
 template <class T, int M, int WV, int R = 3>
 __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, const int (&off)[2 * R], T gm1,

@@ -609,6 +609,15 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
 #pragma unroll
       for (int c = 0; c < M; ++c) qp[c] = col[off + c * cs];
     }
+    const int r = k - 1;   // cell row finished by this lane
+    const bool upd = MODE != MODE_FLUX && act && r >= y0 && r < ylast;
+    const size_t idx = (size_t)r * nx + x;
+    // the x-sweep's part of this row's update, fetched before the fluxes
+    double lx[M];
+    if (upd) {
+#pragma unroll
+      for (int c = 0; c < M; ++c) lx[c] = a.lx[c * cs + idx];
+    }
     if (act) {
       T F[M];
       int off[2 * R];
@@ -627,14 +636,8 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
       }
     }
     wave_sync();
-    const int r = k - 1;   // cell row finished by this lane
-    if (MODE != MODE_FLUX && act && r >= y0 && r < ylast) {
-      const size_t idx = (size_t)r * nx + x;
-      double lx[M], qnew[M];
-      // every load before the first store: out never overlaps lx, but the
-      // compiler cannot know that and would serialise them
-#pragma unroll
-      for (int c = 0; c < M; ++c) lx[c] = a.lx[c * cs + idx];
+    if (upd) {
+      double qnew[M];
 #pragma unroll
       for (int c = 0; c < M; ++c) {
         const double L = -(fw[fk][c][cl] - fw[fkm][c][cl]) * a.g.inv_dy;
