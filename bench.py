@@ -63,10 +63,10 @@ def sweep_bytes(nx, ny, d):
     return cells * 32 * 8 // 3 if d == "x" else cells * 32 * 3
 
 
-# Measured HBM traffic of the dominant kernel (rocprofv3 FETCH_SIZE and
-# WRITE_SIZE, scaled by the same counters on a plain copy): valid only while
-# the kernel sources hash to the value recorded next to the figure.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_y_2d_euler_2048_fp64_traffic.md")
+# Measured HBM traffic of the sweeps (rocprofv3 FETCH_SIZE and WRITE_SIZE,
+# scaled by the same counters on a plain copy): valid only while the kernel
+# sources hash to the value recorded next to the figures.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_xy_2d_euler_2048_fp64_traffic.md")
 KERNEL_SOURCES = ("za_device.hpp", "za_kernels.hpp", "za_lib.hip")
 
 
@@ -91,10 +91,10 @@ def measured_traffic(kernel):
         if ":" in ln and ln.startswith("- "):
             k, v = ln[2:].split(":", 1)
             rec[k.strip()] = v.strip().strip("`")
-    if rec.get("kernel") != kernel or rec.get("sources_sha256") != kernel_sources_sha256():
+    if rec.get("sources_sha256") != kernel_sources_sha256():
         return None
     try:
-        return float(rec["traffic_bytes_per_launch"])
+        return float(rec["traffic " + kernel])
     except (KeyError, ValueError):
         return None
 
