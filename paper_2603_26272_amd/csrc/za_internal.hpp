@@ -23,6 +23,7 @@ struct za_ctx {
   za::DevCtl* ctl = nullptr; // device control block
   int red_blocks = 1;
   int ytile = 64;            // y-sweep rows per block
+  int xl_chunks = 0;         // looped x-sweep chunks per row segment (0: one-shot sweep)
   int stage_blocks = 1;      // blocks of the kernel that writes a stage state
   int part_blocks = 1;       // capacity of `part` in blocks
   bool speeds_valid = false; // part holds the wave speeds of the current q

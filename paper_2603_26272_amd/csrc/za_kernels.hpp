@@ -399,6 +399,7 @@ struct SweepArgs {
   int check_active;      // stepping: skip when the integration is inactive
   int ytile;             // y-sweep: at most this many rows per block (band)
   double* part;          // MODE_STAGE: per-block wave-speed maxima of the new state
+  int xl_chunks;         // looped x-sweep: 64-interface chunks per row segment
 };
 
 template <class T>
@@ -520,6 +521,125 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
     }
   }
   if (MODE == MODE_STAGE && a.part) block_max_store(rs, a.part + (size_t)bid * NPART);
+}
+
+// ---------------------------------------------------------------------------
+// Looped x-sweep of the 2D stage (MODE_LX, FP64 records): one wavefront per
+// row segment of 64 nc - 1 cells, walked in nc chunks of 64 interfaces.  Lane
+// l of chunk j computes interface I0 + l (I0 = s0 + 64 j) from a 128-cell LDS
+// ring of records; each chunk first adds the next 64 cells to the ring (their
+// state was loaded while the previous chunk computed its fluxes) and then
+// completes the partial stage of cell I0 - 1 + l, whose left flux the
+// previous chunk's lane 63 left in a carry slot.  Every record is built once
+// per segment, and neighbouring segments share one interface, so a row of
+// 2048 cells takes the same 33 flux passes as the one-shot sweep with half
+// its record passes.
+// ---------------------------------------------------------------------------
+constexpr int XL_RING = 128;
+
+__device__ __forceinline__ int xl_slot(int k) { return k & (XL_RING - 1); }
+
+template <int SYS, int M>
+__device__ __forceinline__ void xl_load(const double* __restrict__ row, size_t cs, int j, double (&qp)[M]) {
+#pragma unroll
+  for (int c = 0; c < M; ++c) qp[c] = row[(size_t)j + c * cs];
+}
+
+template <int SYS, int M>
+__device__ __forceinline__ void xl_record(const double (&qp)[M], const Phys& ph, double* rec) {
+  if (SYS == SYS_EULER) {
+    euler_record<double, (M == 1 ? 4 : M)>(*reinterpret_cast<const double(*)[(M == 1 ? 4 : M)]>(qp), ph.gm1, rec,
+                                           XL_RING);
+  } else {
+    rec[0] = qp[0];
+    rec[XL_RING] = scalar_f<SYS, double>(qp[0], ph.adv[0]);
+  }
+}
+
+template <int SYS, int M, int WV>
+__device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<double>& cfg, int bid) {
+  constexpr int R = 3;
+  if (a.check_active && !a.ctl->active) return;
+  const SweepConst sk = sweep_const<0>(a.ctl, a.g, false, true);
+  constexpr int NF = NumFields<SYS, M>::value;
+  __shared__ double xr[4][NF * XL_RING];
+  __shared__ double fl[4][M][66];   // [l + 1]: flux of lane l; [65]: carry from the previous chunk
+  const int lane = threadIdx.x & 63, wv = wave_id();
+  const int nx = a.g.nx, ny = a.g.ny;
+  const int nc = a.xl_chunks;
+  const int seg_cells = 64 * nc - 1;
+  const int nseg = (nx + seg_cells - 1) / seg_cells;
+  const int wid = bid * 4 + wv;
+  const int line = wid / nseg, seg = wid - line * nseg;   // wave-uniform
+  if (line >= ny) return;   // the wavefronts of a block never wait for each other
+  const int s0 = seg * seg_cells;
+  const int nch = min(nc, (nx - s0) / 64 + 1);   // chunks holding interfaces <= nx
+  const size_t cs = (size_t)nx * ny;
+  const double* const rowq = a.q + (size_t)line * nx;
+  double* const ring = &xr[wv][0];
+  double(*const fw)[66] = fl[wv];
+  const int bcx = a.g.bc_x;
+  // ring slot of cell k is (k - s0 + R) mod 128; cells s0 - R .. s0 - R + 63 first
+  double qp[M];
+  xl_load<SYS, M>(rowq, cs, bc_map(s0 - R + lane, nx, bcx), qp);
+  xl_record<SYS, M>(qp, a.ph, ring + lane);
+  xl_load<SYS, M>(rowq, cs, bc_map(s0 - R + 64 + lane, nx, bcx), qp);
+  for (int j = 0; j < nch; ++j) {
+    const int I0 = s0 + 64 * j;
+    // the 64 cells this chunk adds: I0 + 64 - R + lane, over the slots of
+    // cells I0 - 64 - R + lane, which the previous chunk was the last to read
+    xl_record<SYS, M>(qp, a.ph, ring + xl_slot(64 * j + 64 + lane));
+    wave_sync();
+    if (j + 1 < nch) xl_load<SYS, M>(rowq, cs, bc_map(I0 + 128 - R + lane, nx, bcx), qp);
+    // the cell this lane completes, and its Q^n (fetched before the fluxes)
+    const int i = I0 - 1 + lane;
+    const bool upd = (j > 0 || lane > 0) && i < nx;
+    double qb[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) qb[c] = 0.0;
+    if (upd && a.ca != 0.0) {
+#pragma unroll
+      for (int c = 0; c < M; ++c) qb[c] = a.qn[c * cs + (size_t)line * nx + i];
+    }
+    const int I = I0 + lane;
+    double F[M];
+    if (I <= nx) {
+      int off[2 * R];
+#pragma unroll
+      for (int jj = 0; jj < 2 * R; ++jj) off[jj] = xl_slot(64 * j + lane + jj);
+      stencil_flux<SYS, M, 0, double, WV, R>(ring, XL_RING, off, a.ph, sk, cfg.w, F);
+#pragma unroll
+      for (int c = 0; c < M; ++c) fw[c][lane + 1] = F[c];
+    }
+    wave_sync();
+    if (upd) {
+      const int si = xl_slot(64 * j + lane - 1 + R);
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        double qc;
+        if (SYS == SYS_EULER) {
+          typedef RecLayout<(M == 1 ? 4 : M)> Lo;
+          const int f = c == 0 ? (int)Lo::Q0 : (c == M - 1 ? (int)Lo::E : (c == 1 ? (int)Lo::Q1 : (int)Lo::Q2));
+          qc = ring[f * XL_RING + si];
+        } else {
+          qc = ring[si];
+        }
+        const double Fm = lane == 0 ? fw[c][65] : fw[c][lane];
+        const double L = -(fw[c][lane + 1] - Fm) * a.g.inv_dx;
+        a.out[c * cs + (size_t)line * nx + i] = fma(a.ca, qb[c], a.cb * fma(sk.dt, L, qc));
+      }
+    }
+    wave_sync();
+    if (lane == 63 && I <= nx) {
+#pragma unroll
+      for (int c = 0; c < M; ++c) fw[c][65] = fw[c][64];
+    }
+  }
+}
+
+template <int SYS, int M, int WV>
+__global__ __launch_bounds__(256, 3) void k_sweep_xl(SweepArgs a, CfgArg<double> cfg) {
+  sweep_xl_body<SYS, M, WV>(a, cfg, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -84,6 +84,7 @@ __device__ __forceinline__ SweepArgs slot_args(const SlotDesc& d, int stage, boo
   a.check_active = 1;
   a.ytile = SERVE_YTILE;
   a.part = d.part;
+  a.xl_chunks = 0;
   return a;
 }
 
