@@ -113,7 +113,10 @@ typedef struct {
  * hip_stream: a hipStream_t (NULL = the default stream).  Allocates the
  * workspace (two RK3 stage states, the x-sweep partial RHS in 2D, the
  * reduction partials and a device control block).  *out receives the
- * context; on error *out is NULL. */
+ * context; on error *out is NULL.  Launch shapes are fixed here; the
+ * environment variable ZA_XL_CHUNKS, read at this call, sets the chunks of
+ * 64 interfaces per row segment of the looped 2D x-sweep (0: one-shot
+ * sweep; results are identical either way). */
 za_status za_ctx_create(const za_problem* problem, void* hip_stream, za_ctx** out);
 za_status za_ctx_destroy(za_ctx* ctx);
 /* Rebind the stream used by later calls. */
