@@ -678,7 +678,7 @@ __device__ __forceinline__ void progress_prio(int st, int nst) {
 // One wavefront's tile: columns x0 .. x0+YS_COLS-1, cell rows [y0, ylast)
 // (interfaces y0 .. ylast).  MODE_STAGE folds the wave speeds of the new
 // states into rs.
-template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0>
+template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0, bool LXPRE = true>
 __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>& cfg, const SweepConst& sk, int x0,
                                              int y0, int ylast, double (&rs)[NPART]) {
   constexpr int YS_RING = ys_ring(R);
@@ -733,8 +733,9 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
     const bool upd = MODE != MODE_FLUX && act && r >= y0 && r < ylast;
     const size_t idx = (size_t)r * nx + x;
     // the x-sweep's part of this row's update, fetched before the fluxes
+    // (LXPRE; otherwise after them, for callers short of registers)
     double lx[M];
-    if (upd) {
+    if (LXPRE && upd) {
 #pragma unroll
       for (int c = 0; c < M; ++c) lx[c] = a.lx[c * cs + idx];
     }
@@ -758,6 +759,10 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
     wave_sync();
     if (upd) {
       double qnew[M];
+      if (!LXPRE) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) lx[c] = a.lx[c * cs + idx];
+      }
 #pragma unroll
       for (int c = 0; c < M; ++c) {
         const double L = -(fw[fk][c][cl] - fw[fkm][c][cl]) * a.g.inv_dy;
@@ -801,7 +806,7 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
 
 // Block (bx, by) owns 64 columns, one YS_COLS-column tile per wavefront, and
 // band by of the ceil(ny / ytile) bands of (near) equal height.
-template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0>
+template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0, bool LXPRE = true>
 __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>& cfg, int bx, int by, int gx) {
   if (a.check_active && !a.ctl->active) return;
   const SweepConst sk = sweep_const<1>(a.ctl, a.g, PP && SYS == SYS_EULER && MODE == MODE_STAGE, true);
@@ -811,7 +816,7 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
   const int ny = a.g.ny;
   const int nb = (ny + a.ytile - 1) / a.ytile;
   const int y0 = (int)((long long)by * ny / nb), ylast = (int)((long long)(by + 1) * ny / nb);
-  sweep_y_tile<SYS, M, T, MODE, WV, R, PP>(a, cfg, sk, bx * 64 + wave_id() * YS_COLS, y0, ylast, rs);
+  sweep_y_tile<SYS, M, T, MODE, WV, R, PP, LXPRE>(a, cfg, sk, bx * 64 + wave_id() * YS_COLS, y0, ylast, rs);
   if (MODE == MODE_STAGE && a.part)
     block_max_store(rs, a.part + ((size_t)by * gx + bx) * NPART);
 }

@@ -101,8 +101,11 @@ __device__ __forceinline__ CfgArg<T> slot_cfg(const SlotDesc& d) {
   return c;
 }
 
+#ifndef ZA_SRV_XS_WAVES
+#define ZA_SRV_XS_WAVES 3   // the slot lookup costs registers: four waves per SIMD would spill
+#endif
 template <int M, class T>
-__global__ __launch_bounds__(256, ZA_XS_WAVES) void kb_sweep_x(const BatchTable* __restrict__ tab, int stage) {
+__global__ __launch_bounds__(256, ZA_SRV_XS_WAVES) void kb_sweep_x(const BatchTable* __restrict__ tab, int stage) {
   const int b = blockIdx.x;
   if (b >= tab->xtot) return;
   const int s = find_slot(tab->xoff, tab->n, b);
@@ -124,7 +127,8 @@ __global__ __launch_bounds__(256, ZA_YS_WAVES) void kb_sweep_y(const BatchTable*
   const SweepArgs a = slot_args(d, stage, false);
   const CfgArg<T> cfg = slot_cfg<T>(d);
   const int local = b - tab->yoff[s];
-  sweep_y_body<SYS_EULER, 4, T, MODE_STAGE, WV_Z1>(a, cfg, local % d.ystrips, local / d.ystrips, d.ystrips);
+  sweep_y_body<SYS_EULER, 4, T, MODE_STAGE, WV_Z1, 3, 0, false>(a, cfg, local % d.ystrips, local / d.ystrips,
+                                                                 d.ystrips);
 }
 
 __global__ __launch_bounds__(64) void kb_final(const BatchTable* __restrict__ tab, int kind, int dim) {
