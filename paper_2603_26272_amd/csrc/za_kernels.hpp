@@ -860,7 +860,20 @@ __global__ __launch_bounds__(256, WAVES) void k_sweep_y_r(SweepArgs a, CfgArg<T>
 }
 
 
-enum FinalKind { FIN_RHS = 0, FIN_STAGE0 = 1, FIN_STAGEK = 2 };
+__device__ __forceinline__ void step_end_body(DevCtl* ctl) {
+  if (threadIdx.x != 0 || !ctl->active) return;
+  const double dt = ctl->dt;
+  ctl->t = ctl->last ? ctl->t_final : ctl->t + dt;
+  ctl->steps += 1;
+  ctl->dt_min = fmin(ctl->dt_min, dt);
+  ctl->dt_max = fmax(ctl->dt_max, dt);
+  if (ctl->last) ctl->active = 0;
+  if (ctl->max_steps > 0 && ctl->steps >= ctl->max_steps) ctl->active = 0;
+}
+
+// FIN_END_STAGE0: the previous step's end (step_end_body), then FIN_STAGE0,
+// in one launch.
+enum FinalKind { FIN_RHS = 0, FIN_STAGE0 = 1, FIN_STAGEK = 2, FIN_END_STAGE0 = 3 };
 
 __device__ __forceinline__ void wave_final_body(const double* __restrict__ part, int nblk, DevCtl* ctl,
                                                 const Geom& g, const Phys& ph, int dim, int kind, int sys) {
@@ -876,6 +889,10 @@ __device__ __forceinline__ void wave_final_body(const double* __restrict__ part,
     for (int off = 32; off > 0; off >>= 1) r[i] = wave_max(r[i], __shfl_xor(r[i], off, 64));
   }
   if (threadIdx.x != 0) return;
+  if (kind == FIN_END_STAGE0) {
+    step_end_body(ctl);
+    kind = FIN_STAGE0;
+  }
   if (kind != FIN_RHS && !ctl->active) return;
   const bool bad = !(r[0] < __builtin_huge_val());
   double sx = wave_max(r[0], r[2]), sy = wave_max(r[3], r[5]);
@@ -928,16 +945,6 @@ __global__ __launch_bounds__(64) void k_wave_final(const double* __restrict__ pa
   wave_final_body(part, nblk, ctl, g, ph, dim, kind, sys);
 }
 
-__device__ __forceinline__ void step_end_body(DevCtl* ctl) {
-  if (threadIdx.x != 0 || !ctl->active) return;
-  const double dt = ctl->dt;
-  ctl->t = ctl->last ? ctl->t_final : ctl->t + dt;
-  ctl->steps += 1;
-  ctl->dt_min = fmin(ctl->dt_min, dt);
-  ctl->dt_max = fmax(ctl->dt_max, dt);
-  if (ctl->last) ctl->active = 0;
-  if (ctl->max_steps > 0 && ctl->steps >= ctl->max_steps) ctl->active = 0;
-}
 
 static __global__ void k_step_end(DevCtl* ctl) { step_end_body(ctl); }
 

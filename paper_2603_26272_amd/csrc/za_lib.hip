@@ -378,7 +378,9 @@ static int pick_xl_chunks(za_ctx* c) {
 // writes a stage's new state also leaves the per-block wave-speed maxima of
 // that state in c->part, so only the first step of an API call needs a
 // stand-alone reduction pass.
-static za_status enqueue_step(za_ctx* c, double* q) {
+// merge_end: the previous step deferred its end to this step's first final
+// reduction; defer_end: leave this step's end to the next step.
+static za_status enqueue_step(za_ctx* c, double* q, bool merge_end = false, bool defer_end = false) {
   const double ca[3] = {0.0, 0.75, 1.0 / 3.0};
   const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
   const double* in[3] = {q, c->q1, c->q2};
@@ -386,9 +388,10 @@ static za_status enqueue_step(za_ctx* c, double* q) {
   for (int s = 0; s < 3; ++s) {
     const int kind = s == 0 ? FIN_STAGE0 : FIN_STAGEK;
     if (s == 0 && !c->speeds_valid) {
+      if (merge_end) hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, c->stream, c->ctl);
       launch_wave(c, in[s], kind, 1);
     } else {
-      launch_final(c, kind, c->stage_blocks);
+      launch_final(c, s == 0 && merge_end ? FIN_END_STAGE0 : kind, c->stage_blocks);
     }
     SweepArgs a = base_args(c);
     a.check_active = 1;
@@ -408,7 +411,7 @@ static za_status enqueue_step(za_ctx* c, double* q) {
       launch_y(c, MODE_STAGE, a);
     }
   }
-  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, c->stream, c->ctl);
+  if (!defer_end) hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, c->stream, c->ctl);
   c->speeds_valid = true;
   ZA_CHECK_LAUNCH(c, "step launch");
   return ZA_OK;
@@ -437,7 +440,10 @@ static za_status enqueue_steps(za_ctx* c, double* q, int64_t n) {
         c->stream = c->capture_stream;
         hipGraph_t g = nullptr;
         bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        for (int i = 0; ok && i < GRAPH_STEPS; ++i) ok = enqueue_step(c, q) == ZA_OK;
+        // inside the graph each step's end runs with the next step's first
+        // final reduction; the graph's last step ends on its own
+        for (int i = 0; ok && i < GRAPH_STEPS; ++i)
+          ok = enqueue_step(c, q, i > 0, i + 1 < GRAPH_STEPS) == ZA_OK;
         ok = (hipStreamEndCapture(c->stream, &g) == hipSuccess) && ok;
         c->stream = user;
         if (ok) ok = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0) == hipSuccess;
@@ -457,8 +463,11 @@ static za_status enqueue_steps(za_ctx* c, double* q, int64_t n) {
       done += GRAPH_STEPS;
     }
   }
-  for (; done < n; ++done)
-    if ((st = enqueue_step(c, q)) != ZA_OK) return st;
+  for (bool pending = false; done < n; ++done) {
+    const bool defer = done + 1 < n;
+    if ((st = enqueue_step(c, q, pending, defer)) != ZA_OK) return st;
+    pending = defer;
+  }
   return ZA_OK;
 }
 
