@@ -496,7 +496,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one MI355X "
+        print(f"bench.py: --gpus {args.gpus} is not supported; the library runs on one MI355X "
               f"(the multi-GPU slab decomposition is a design note only)", file=sys.stderr)
         sys.exit(2)
 

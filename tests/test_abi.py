@@ -50,6 +50,22 @@ def test_order_validation_host_side():
     assert za.state_count(Problem(dim=1, nx=40, order=3).fp32()) == 3 * 40
 
 
+def test_option_validation_host_side():
+    """tau' (r = 3 only) and the positivity limiter (Euler, FP64, r = 3,
+    cfl <= 0.5, CFL rule) are checked before any device work."""
+    from paper_2603_26272_amd import za
+    from paper_2603_26272_amd.problem import ADVECTION, Problem
+    ok = lambda P: za.state_count(P) > 0
+    assert ok(Problem(dim=1, nx=40, alt_tau=1)) and ok(Problem(dim=1, nx=40, alt_tau=1).fp32())
+    assert not ok(Problem(dim=1, nx=40, alt_tau=2))
+    assert not ok(Problem(dim=1, nx=40, alt_tau=1, order=4))
+    assert ok(Problem(dim=2, nx=16, ny=16, pp_limiter=1))
+    for bad in (Problem(dim=1, nx=40, pp_limiter=1, system=ADVECTION), Problem(dim=1, nx=40, pp_limiter=1, cfl=0.9),
+                Problem(dim=1, nx=40, pp_limiter=1, dt_rule=1), Problem(dim=1, nx=40, pp_limiter=1).fp32(),
+                Problem(dim=1, nx=40, pp_limiter=1, order=4), Problem(dim=1, nx=40, pp_limiter=2)):
+        assert not ok(bad), bad
+
+
 def test_problem_struct_layout_matches_header(tmp_path):
     """The binding's ctypes mirror of za_problem has the C layout (size and
     every field offset), checked with the host C compiler."""
