@@ -573,6 +573,8 @@ def main():
                    "t_final": info["t"]},
         "roofline": roofline,
         "kernels": kernels,
+        # scalar WENO reconstructions: 2 splits x 4 characteristic fields per IR
+        "split_field_recons_per_s": 8 * value,
     }
 
     if not args.no_fp32:
