@@ -218,25 +218,31 @@ __global__ __launch_bounds__(256) void k_wave_partial(const double* __restrict__
 template <int SYS, int M>
 struct NumFields { enum { value = (SYS == SYS_EULER) ? RecLayout<(M == 1 ? 4 : M)>::NF : 2 }; };
 
-// Gather cell `cell` (already boundary-mapped) of the line at `base` and build
-// its record at rec (field stride fs).
-template <int SYS, int M, int DIR, class T>
-__device__ __forceinline__ void stage_cell(const double* __restrict__ base, size_t cs, size_t off,
-                                           const Phys& ph, T* rec, int fs) {
-  if (SYS == SYS_EULER) {
-    double qd[M];
-    if (M == 4 && DIR == 1) {
-      qd[0] = base[off];
-      qd[1] = base[off + 2 * cs];
-      qd[2] = base[off + cs];
-      qd[3] = base[off + 3 * cs];
-    } else {
+// Gather cell `off` (already boundary-mapped) of the line at `base` in the
+// sweep-normal frame (DIR = 1 swaps the two momenta), and build a record at
+// rec (field stride fs) from such a state.  Callers that stage several cells
+// issue every load before the first record so the latencies overlap.
+template <int SYS, int M, int DIR>
+__device__ __forceinline__ void cell_load(const double* __restrict__ base, size_t cs, size_t off, double (&qd)[M]) {
+  if (SYS == SYS_EULER && M == 4 && DIR == 1) {
+    qd[0] = base[off];
+    qd[1 % M] = base[off + 2 * cs];
+    qd[2 % M] = base[off + cs];
+    qd[3 % M] = base[off + 3 * cs];
+  } else if (SYS == SYS_EULER) {
 #pragma unroll
-      for (int c = 0; c < M; ++c) qd[c] = base[off + c * cs];
-    }
+    for (int c = 0; c < M; ++c) qd[c] = base[off + c * cs];
+  } else {
+    qd[0] = base[off];
+  }
+}
+
+template <int SYS, int M, int DIR, class T>
+__device__ __forceinline__ void cell_record(const double (&qd)[M], const Phys& ph, T* rec, int fs) {
+  if (SYS == SYS_EULER) {
     euler_record<T, (M == 1 ? 4 : M)>(*reinterpret_cast<const double(*)[(M == 1 ? 4 : M)]>(qd), (T)ph.gm1, rec, fs);
   } else {
-    const T u = (T)base[off];
+    const T u = (T)qd[0];
     rec[0] = u;
     rec[fs] = scalar_f<SYS, T>(u, (T)ph.adv[DIR]);
   }
@@ -443,9 +449,18 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
   const size_t cs = (size_t)nx * ny;
   const size_t row = (size_t)line * nx;
   if (live) {
-    for (int idx = lane; idx < XS_CELLS + 2 * R; idx += 64) {
-      const int j = bc_map(c0 - R + idx, nx, a.g.bc_x);
-      stage_cell<SYS, M, 0, T>(a.q + row, cs, (size_t)j, a.ph, &xr[wv][idx], XS_REC);
+    constexpr int NX = (XS_CELLS + 2 * R + 63) / 64;   // record passes
+    double qx[NX][M];
+#pragma unroll
+    for (int t = 0; t < NX; ++t) {
+      const int idx = lane + 64 * t;
+      if (idx < XS_CELLS + 2 * R)
+        cell_load<SYS, M, 0>(a.q + row, cs, (size_t)bc_map(c0 - R + idx, nx, a.g.bc_x), qx[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < NX; ++t) {
+      const int idx = lane + 64 * t;
+      if (idx < XS_CELLS + 2 * R) cell_record<SYS, M, 0, T>(qx[t], a.ph, &xr[wv][idx], XS_REC);
     }
   }
   wave_sync();   // the records and fluxes of a wavefront are its own
@@ -581,9 +596,12 @@ __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<d
   const int bcx = a.g.bc_x;
   // ring slot of cell k is (k - s0 + R) mod 128; cells s0 - R .. s0 - R + 63 first
   double qp[M];
-  xl_load<SYS, M>(rowq, cs, bc_map(s0 - R + lane, nx, bcx), qp);
-  xl_record<SYS, M>(qp, a.ph, ring + lane);
-  xl_load<SYS, M>(rowq, cs, bc_map(s0 - R + 64 + lane, nx, bcx), qp);
+  {
+    double q0[M];   // both loads in flight before the first records
+    xl_load<SYS, M>(rowq, cs, bc_map(s0 - R + lane, nx, bcx), q0);
+    xl_load<SYS, M>(rowq, cs, bc_map(s0 - R + 64 + lane, nx, bcx), qp);
+    xl_record<SYS, M>(q0, a.ph, ring + lane);
+  }
   for (int j = 0; j < nch; ++j) {
     const int I0 = s0 + 64 * j;
     // the 64 cells this chunk adds: I0 + 64 - R + lane, over the slots of
@@ -700,10 +718,18 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
   // interface k is (k - y0 + 1) mod YS_FSLOT.  Both advance by YS_ROWS per
   // step, so each lane carries them (scaled) instead of dividing.
   // rows y0-R .. y0+YS_ROWS+R-2 for the first step
-  for (int i = g; i < YS_RING; i += YS_ROWS) {
-    if (xin) {
-      const int r = y0 - R + i;
-      stage_cell<SYS, M, 1, T>(col, cs, (size_t)bc_map(r, ny, a.g.bc_y) * nx, a.ph, rw + i * RS, YS_COLS);
+  {
+    constexpr int NPRO = (YS_RING + YS_ROWS - 1) / YS_ROWS;
+    double qr[NPRO][M];
+#pragma unroll
+    for (int t = 0; t < NPRO; ++t) {
+      const int i = g + YS_ROWS * t;
+      if (xin && i < YS_RING) cell_load<SYS, M, 1>(col, cs, (size_t)bc_map(y0 - R + i, ny, a.g.bc_y) * nx, qr[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < NPRO; ++t) {
+      const int i = g + YS_ROWS * t;
+      if (xin && i < YS_RING) cell_record<SYS, M, 1, T>(qr[t], a.ph, rw + i * RS, YS_COLS);
     }
   }
   wave_sync();

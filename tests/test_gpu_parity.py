@@ -344,3 +344,19 @@ def test_full_length_1d_drift_bounded_by_self_sensitivity(dev):
     gpu_drift = (np.abs(q.cpu().numpy() - ref) / scale).max()
     assert self_sens > 1e-10            # the problem itself is this sensitive
     assert gpu_drift <= 10 * self_sens, (gpu_drift, self_sens)
+
+
+def test_two_steps_full_size_against_oracle(dev):
+    """Two RK3 steps of the 2D Euler workload at 2048^2 in the benchmark's
+    launch configuration (looped x-sweep, banded y-sweep, wave-speed maxima
+    fused into the stage epilogue, step end merged into the next reduction),
+    every cell against the oracle's two steps."""
+    P, q0 = W.quadrants_2d(0, 2048)
+    q = torch.from_numpy(q0).to(dev)
+    with Ctx(P) as ctx:
+        info = ctx.solve(q, 0.0, 2)
+    orc.set_threads(16)
+    ref, steps, t, st = orc.solve(P, q0, 0.0, 2)
+    assert st == 0 and steps == 2 and info["steps"] == 2
+    assert abs(info["t"] - t) <= 1e-14 * t
+    assert_close(q.cpu().numpy(), ref, 1e-10, "2048^2, two steps")
