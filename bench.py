@@ -136,10 +136,19 @@ def cpu_baseline(P, q0_np, seconds):
             break
     dt = time.perf_counter() - t0
     irs = n * ir_per_rhs(P.nx, P.ny) / dt
-    return {"value": irs, "unit": "IR/s", "cores": used, "kind": "oracle",
-            "sample": f"{n} full right-hand side(s) of the 2D Euler {P.nx}x{P.ny} workload "
-                      f"(one RK3 stage each, {ir_per_rhs(P.nx, P.ny)} IR) in {dt:.1f} s, FP64, "
-                      f"OpenMP over rows"}
+    out = {"value": irs, "unit": "IR/s", "cores": used, "kind": "oracle",
+           "sample": f"{n} full right-hand side(s) of the 2D Euler {P.nx}x{P.ny} workload "
+                     f"(one RK3 stage each, {ir_per_rhs(P.nx, P.ny)} IR) in {dt:.1f} s, FP64, "
+                     f"OpenMP over rows"}
+    # the same oracle on one thread (one right-hand side), for reference
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.rhs(P, q0_np)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    out["single_thread"] = {"value": ir_per_rhs(P.nx, P.ny) / dt1, "unit": "IR/s", "cores": 1,
+                            "sample": f"one full right-hand side in {dt1:.1f} s"}
+    return out
 
 
 def run_serving(lam, n_requests, budget, slots, seed=None, max_1d=65536, max_2d=1024):
