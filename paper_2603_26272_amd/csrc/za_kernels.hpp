@@ -903,16 +903,33 @@ enum FinalKind { FIN_RHS = 0, FIN_STAGE0 = 1, FIN_STAGEK = 2, FIN_END_STAGE0 = 3
 
 __device__ __forceinline__ void wave_final_body(const double* __restrict__ part, int nblk, DevCtl* ctl,
                                                 const Geom& g, const Phys& ph, int dim, int kind, int sys) {
+  // every thread of the block (one or more wavefronts) folds a strided share
+  // of the per-block maxima; the maxima are exact whatever the order
   double r[NPART];
 #pragma unroll
   for (int i = 0; i < NPART; ++i) r[i] = -__builtin_huge_val();
-  for (int b = threadIdx.x; b < nblk; b += 64) {
+#pragma unroll 2
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
 #pragma unroll
     for (int i = 0; i < NPART; ++i) r[i] = wave_max(r[i], part[(size_t)b * NPART + i]);
   }
 #pragma unroll
   for (int i = 0; i < NPART; ++i) {
     for (int off = 32; off > 0; off >>= 1) r[i] = wave_max(r[i], __shfl_xor(r[i], off, 64));
+  }
+  if (blockDim.x > 64) {
+    __shared__ double red[16][NPART];
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int i = 0; i < NPART; ++i) red[threadIdx.x >> 6][i] = r[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+#pragma unroll
+        for (int i = 0; i < NPART; ++i) r[i] = wave_max(r[i], red[w][i]);
+      }
+    }
   }
   if (threadIdx.x != 0) return;
   if (kind == FIN_END_STAGE0) {
@@ -966,7 +983,7 @@ __device__ __forceinline__ void wave_final_body(const double* __restrict__ part,
 }
 
 template <int M>
-__global__ __launch_bounds__(64) void k_wave_final(const double* __restrict__ part, int nblk, DevCtl* ctl,
+__global__ __launch_bounds__(256) void k_wave_final(const double* __restrict__ part, int nblk, DevCtl* ctl,
                                                    Geom g, Phys ph, int dim, int kind, int sys) {
   wave_final_body(part, nblk, ctl, g, ph, dim, kind, sys);
 }

@@ -258,7 +258,7 @@ static void launch_y(za_ctx* c, int mode, const SweepArgs& a) {
 }
 
 static void launch_final(za_ctx* c, int kind, int nblk) {
-  hipLaunchKernelGGL((k_wave_final<4>), dim3(1), dim3(64), 0, c->stream, c->part, nblk, c->ctl, c->geom, c->ph,
+  hipLaunchKernelGGL((k_wave_final<4>), dim3(1), dim3(256), 0, c->stream, c->part, nblk, c->ctl, c->geom, c->ph,
                      c->prob.dim, kind, (int)c->prob.system);
 }
 
