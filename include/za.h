@@ -98,6 +98,14 @@ typedef struct {
                            /* (13/12) <c_tau,f>^2 + <c'_tau,f>^2 of eq:GSI_alt */
                            /* (r = 3; for the dispersion analysis, Section    */
                            /* 3.2); 0: tau of eq:GSI                           */
+  double  weight_L;        /* L and q of eq:weights_unnormalized,             */
+  double  weight_q;        /* alpha_k = d_k (L + Gamma_k)^q (tab:SpecialCases: */
+                           /* Z and Ai-Z: L = q = 1; JS and Ai-JS: L = 0,     */
+                           /* p = 2).  L >= 0, q >= 1; both 0 select the      */
+                           /* paper's L = q = 1.  With L = 0 the common       */
+                           /* factor tau^(pq) cancels in omega and is left    */
+                           /* out, which also defines omega where tau = 0.    */
+                           /* The server takes L = q = 1 only                 */
 } za_problem;
 
 typedef struct za_ctx za_ctx;

@@ -42,6 +42,8 @@ class _Problem(C.Structure):
         ("order", C.c_int32),
         ("pp_limiter", C.c_int32),
         ("alt_tau", C.c_int32),
+        ("weight_L", C.c_double),
+        ("weight_q", C.c_double),
     ]
 
 
@@ -91,6 +93,12 @@ def lib():
                                       C.c_double, C.c_double, _DP, _DP]
         L.orc_set_order_tables.restype = C.c_int
         L.orc_set_order_tables.argtypes = [C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int]
+        L.orc_recon_lq.restype = C.c_double
+        L.orc_recon_lq.argtypes = [_DP, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double, C.c_double,
+                                   _DP]
+        L.orc_recon_r_lq.restype = C.c_double
+        L.orc_recon_r_lq.argtypes = [C.c_int, _DP, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double,
+                                     C.c_double, _DP]
         L.orc_recon_r.restype = C.c_double
         L.orc_recon_r.argtypes = [C.c_int, _DP, C.c_double, C.c_double, C.c_int, C.c_double, C.c_int,
                                   C.c_int, _DP]
@@ -132,6 +140,8 @@ def _problem(pb) -> _Problem:
     P.order = int(_get(pb, "order", 3))
     P.pp_limiter = int(_get(pb, "pp_limiter", 0))
     P.alt_tau = int(_get(pb, "alt_tau", 0))
+    P.weight_L = float(_get(pb, "weight_L", 1.0))
+    P.weight_q = float(_get(pb, "weight_q", 1.0))
     _ensure_order(P.order)
     return P
 
@@ -195,6 +205,26 @@ def recon_r(r, v, p=1.0, eps=1e-40, ai=0, mu0=1e-40, linear=0, prec=0, detail=Fa
                      "beta_r": d[2 * r + 2], "tau": d[2 * r + 3], "mu": d[2 * r + 4],
                      "omega": d[2 * r + 5:3 * r + 6].copy()}
     return lib().orc_recon_r(int(r), _ptr(v), p, eps, ai, mu0, linear, prec, None)
+
+
+def recon_lq(v6, L, q, p=1.0, eps=1e-40, ai=0, mu0=1e-40, detail=False):
+    """O1 with the weight parameters L and q of eq:weights_unnormalized."""
+    v = np.ascontiguousarray(v6, dtype=np.float64)
+    assert v.shape == (6,)
+    if detail:
+        d = np.zeros(15)
+        r = lib().orc_recon_lq(_ptr(v), p, eps, ai, mu0, L, q, _ptr(d))
+        return r, {"q": d[0:4].copy(), "beta": d[4:9].copy(), "tau": d[9], "mu": d[10],
+                   "omega": d[11:15].copy()}
+    return lib().orc_recon_lq(_ptr(v), p, eps, ai, mu0, L, q, None)
+
+
+def recon_r_lq(r, v, L, q, p=1.0, eps=1e-40, ai=0, mu0=1e-40):
+    """O1 of the order-2r scheme (FP64) with the weight parameters L and q."""
+    _ensure_order(int(r))
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert v.shape == (2 * r,)
+    return lib().orc_recon_r_lq(int(r), _ptr(v), p, eps, ai, mu0, L, q, None)
 
 
 def recon_alt(v6, p=1.0, eps=1e-40, ai=0, mu0=1e-40, detail=False):

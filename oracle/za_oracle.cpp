@@ -133,7 +133,30 @@ struct ReconParams {
   double mu0;      /* mu_0 of eq:aimu                                      */
   int linear;      /* 1: omega = d (the linear sixth-order central flux)   */
   int alt_tau = 0; /* 1: the alternative indicator tau' of eq:GSI_alt      */
+  double L = 1.0;  /* L and q of eq:weights_unnormalized (paper: 1, 1)   */
+  double q = 1.0;
 };
+
+/* Unnormalised weight alpha_k / d_k = (L + Gamma_k)^q of
+ * eq:weights_unnormalized with Gamma_k = (tau / bden)^p (eq:weight_nonlinear),
+ * bden = beta_k + eps mu^2.  Reading for L = 0: alpha_k = d_k tau^(pq) /
+ * bden^(pq); the factor (tau / bmin)^(pq) (bmin the smallest bden of the
+ * stencil) is common to every k and cancels in omega_k (eq:weights_general),
+ * so alpha_k / d_k is taken as (bmin / bden)^(pq) <= 1: omega stays defined
+ * where tau = 0 (the limit tau -> 0+, JS-type weights) and nothing overflows. */
+template <class R>
+static R z_alpha(R tau, R bden, R bmin, const ReconParams& P) {
+  if (P.L == 0.0) {
+    R a = bmin / bden;
+    if (P.p * P.q != 1.0) a = r_pow(a, R(P.p * P.q));
+    return a;
+  }
+  R g = tau / bden;
+  if (P.p != 1.0) g = r_pow(g, R(P.p));
+  R a = R(P.L) + g;
+  if (P.q != 1.0) a = r_pow(a, R(P.q));
+  return a;
+}
 
 /* Constants of the r = 3 scheme, built in the arithmetic type R so that the
  * quad build carries them to quad accuracy.  Values as printed in Section 3:
@@ -239,15 +262,19 @@ static R recon_za6(const R v[6], const ZA6Const<R>& K, const ReconParams& P,
     mu = s / R(6) + R(P.mu0);
   }
 
-  /* Gamma_k (eq:weight_nonlinear), alpha_k = d_k (L + Gamma_k)^q with
-   * L = 1, q = 1 (eq:weights_unnormalized), omega_k (eq:weights_general). */
+  /* Gamma_k (eq:weight_nonlinear), alpha_k = d_k (L + Gamma_k)^q
+   * (eq:weights_unnormalized; the paper's runs: L = q = 1), omega_k
+   * (eq:weights_general). */
   const R eps = R(P.eps);
   const R epsmu2 = P.ai ? eps * (mu * mu) : eps;
+  R bden[4];
+  for (int k = 0; k < 4; ++k) bden[k] = b[k] + epsmu2;
+  R bmin = bden[0];
+  if (P.L == 0.0)
+    for (int k = 1; k < 4; ++k) bmin = bden[k] < bmin ? bden[k] : bmin;
   R alpha[4], asum = R(0);
   for (int k = 0; k < 4; ++k) {
-    R g = tau / (b[k] + epsmu2);
-    if (P.p != 1.0) g = r_pow(g, R(P.p));
-    alpha[k] = K.d[k] * (R(1) + g);
+    alpha[k] = K.d[k] * z_alpha<R>(tau, bden[k], bmin, P);
     asum = asum + alpha[k];
   }
   R omega[4];
@@ -361,11 +388,14 @@ static R recon_gen(const R* v, const GenConst<R>& K, const ReconParams& P, doubl
   }
   const R eps = R(P.eps);
   const R epsmu2 = P.ai ? eps * (mu * mu) : eps;
+  R bden[R_MAX + 1];
+  for (int k = 0; k <= r; ++k) bden[k] = bw[k] + epsmu2;
+  R bmin = bden[0];
+  if (P.L == 0.0)
+    for (int k = 1; k <= r; ++k) bmin = bden[k] < bmin ? bden[k] : bmin;
   R alpha[R_MAX + 1], asum = R(0);
   for (int k = 0; k <= r; ++k) {
-    R g = tau / (bw[k] + epsmu2);
-    if (P.p != 1.0) g = r_pow(g, R(P.p));
-    alpha[k] = K.d[k] * (R(1) + g);
+    alpha[k] = K.d[k] * z_alpha<R>(tau, bden[k], bmin, P);
     asum = asum + alpha[k];
   }
   R omega[R_MAX + 1];
@@ -435,6 +465,7 @@ typedef struct {
   int32_t order;          /* r of the order-2r scheme (0 or 3: WENO-ZA6) */
   int32_t pp_limiter;     /* 1: positivity-preserving flux limiter in steps */
   int32_t alt_tau;        /* 1: tau' of eq:GSI_alt instead of tau (r = 3)   */
+  double weight_L, weight_q; /* L, q of eq:weights_unnormalized (0, 0: 1, 1) */
 } orc_problem;
 }
 
@@ -742,6 +773,9 @@ static int make_ctx(const orc_problem* p, Ctx* C) {
   C->RP.linear = p->linear_weights;
   C->RP.alt_tau = p->alt_tau;
   if (p->alt_tau && C->r != 3) return 1;
+  if (p->weight_L == 0.0 && p->weight_q == 0.0) { C->RP.L = 1.0; C->RP.q = 1.0; }
+  else { C->RP.L = p->weight_L; C->RP.q = p->weight_q; }
+  if (!(C->RP.L >= 0.0) || !(C->RP.q >= 1.0)) return 1;
   C->dx = (p->xhi - p->xlo) / p->nx;
   C->dy = p->dim == 2 ? (p->yhi - p->ylo) / p->ny : 1.0;
   C->ncell = (size_t)p->nx * p->ny;
@@ -1004,6 +1038,17 @@ double orc_recon(const double* v6, double p, double eps, int ai, double mu0, int
   if (detail) std::memcpy(detail, &d, sizeof(d));
   return r;
 }
+/* As orc_recon with the weight parameters L and q of eq:weights_unnormalized. */
+double orc_recon_lq(const double* v6, double p, double eps, int ai, double mu0, double L, double q,
+                    double* detail) {
+  static const ZA6Const<double> K;
+  ReconParams RP{p, eps, ai, mu0, 0};
+  RP.L = L; RP.q = q;
+  ReconDetail d;
+  double r = recon_za6<double>(v6, K, RP, detail ? &d : nullptr);
+  if (detail) std::memcpy(detail, &d, sizeof(d));
+  return r;
+}
 /* As orc_recon with the alternative global indicator tau' (eq:GSI_alt). */
 double orc_recon_alt(const double* v6, double p, double eps, int ai, double mu0, double* detail) {
   static const ZA6Const<double> K;
@@ -1090,6 +1135,16 @@ double orc_recon_r(int r, const double* v, double p, double eps, int ai, double 
     for (int j = 0; j < 2 * r; ++j) x[j] = (quad)v[j];
     return (double)recon_gen<quad>(x, K, RP, nullptr);
   }
+  GenConst<double> K(r);
+  return recon_gen<double>(v, K, RP, detail);
+}
+
+/* orc_recon_r (FP64) with the weight parameters L and q. */
+double orc_recon_r_lq(int r, const double* v, double p, double eps, int ai, double mu0, double L, double q,
+                      double* detail) {
+  if (r < 2 || r > R_MAX || !g_gen[r].set) return NAN;
+  ReconParams RP; RP.p = p; RP.eps = eps; RP.ai = ai; RP.mu0 = mu0; RP.linear = 0;
+  RP.L = L; RP.q = q;
   GenConst<double> K(r);
   return recon_gen<double>(v, K, RP, detail);
 }

@@ -31,6 +31,9 @@ struct WeightCfg {
   int ai;     // 1: affine-invariant descaler
   int linear; // 1: omega = d
   int alt_tau; // 1: tau' of eq:GSI_alt (r = 3, general weights)
+  T L;        // L of eq:weights_unnormalized (1 on the fast path)
+  T q;        // q of eq:weights_unnormalized (1 on the fast path)
+  T pq;       // p q (the exponent when L = 0)
 };
 
 // Weight variants compiled as separate kernels: the paper's Z weights with
@@ -77,6 +80,27 @@ __device__ __forceinline__ double sqrt_nr(double x) {
 }
 __device__ __forceinline__ float sqrt_nr(float x) { return sqrtf(x); }
 __device__ __forceinline__ float div_nr(float a, float x) { return a * __builtin_amdgcn_rcpf(x); }
+
+// alpha_k / d_k = (L + Gamma_k)^q (eq:weights_unnormalized), Gamma_k =
+// (tau / b)^p (eq:weight_nonlinear), b = beta_k + eps mu^2 on the common
+// scale of the caller.  L = 0: tau^(pq) is common to every k and cancels in
+// omega_k, and so does bmin^(-pq) (bmin the smallest b of the stencil), so the
+// weight is taken as (bmin / b)^(pq) <= 1, defined where tau = 0 and free of
+// overflow.  Outside WV_GENERAL this is the paper's 1 + tau / b.
+template <class T, int WV>
+__device__ __forceinline__ T z_alpha(T tau, T b, T bmin, const WeightCfg<T>& w) {
+  if (WV == WV_GENERAL && w.L == T(0)) {
+    T a = bmin * rcp_nr(b);
+    if (w.pq != T(1)) a = pow(a, w.pq);
+    return a;
+  }
+  T g = tau * rcp_nr(b);
+  if (WV == WV_GENERAL && w.p != T(1)) g = pow(g, w.p);
+  if (WV != WV_GENERAL) return T(1) + g;
+  T a = w.L + g;
+  if (w.q != T(1)) a = pow(a, w.q);
+  return a;
+}
 
 // ---------------------------------------------------------------------------
 // One WENO-ZA6 reconstruction at x_{i+1/2} (Section 3: r = 3).
@@ -179,11 +203,9 @@ __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const Weigh
     eps = w.eps4;
   }
   const T b0 = B0 + eps, b1 = B1 + eps, b2 = B2 + eps, b3 = B3 + eps;
-  T g0w = tau * rcp_nr(b0), g1w = tau * rcp_nr(b1), g2w = tau * rcp_nr(b2), g3w = tau * rcp_nr(b3);
-  if (WV == WV_GENERAL && w.p != T(1)) {
-    g0w = pow(g0w, w.p); g1w = pow(g1w, w.p); g2w = pow(g2w, w.p); g3w = pow(g3w, w.p);
-  }
-  const T a0 = T(1) + g0w, a1 = T(9) * (T(1) + g1w), a2 = T(9) * (T(1) + g2w), a3 = T(1) + g3w;
+  const T bmin = (WV == WV_GENERAL && w.L == T(0)) ? fmin(fmin(b0, b1), fmin(b2, b3)) : T(0);
+  const T a0 = z_alpha<T, WV>(tau, b0, bmin, w), a1 = T(9) * z_alpha<T, WV>(tau, b1, bmin, w),
+          a2 = T(9) * z_alpha<T, WV>(tau, b2, bmin, w), a3 = z_alpha<T, WV>(tau, b3, bmin, w);
   return div_nr(fma(a0, q0, fma(a1, q1, fma(a2, q2, a3 * q3))), (a0 + a1) + (a2 + a3));
 }
 
@@ -257,12 +279,16 @@ __device__ __forceinline__ T zar(const T (&s)[2 * R], const WeightCfg<T>& w) {
     tau *= imu2;
     eps = w.eps1;
   }
+  T bmin = T(0);
+  if (WV == WV_GENERAL && w.L == T(0)) {
+    bmin = beta[0] + eps;
+#pragma unroll
+    for (int k = 1; k <= R; ++k) bmin = fmin(bmin, beta[k] + eps);
+  }
   T num = T(0), den = T(0);
 #pragma unroll
   for (int k = 0; k <= R; ++k) {
-    T gk = tau * rcp_nr(beta[k] + eps);
-    if (WV == WV_GENERAL && w.p != T(1)) gk = pow(gk, w.p);
-    const T a = T(Tb::d(k)) * (T(1) + gk);
+    const T a = T(Tb::d(k)) * z_alpha<T, WV>(tau, beta[k] + eps, bmin, w);
     num = fma(a, q[k], num);
     den += a;
   }

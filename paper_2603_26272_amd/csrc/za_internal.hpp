@@ -45,8 +45,13 @@ inline int order_of(const za_problem& p) { return p.order == 0 ? 3 : p.order; }
 
 // Z weights with p = 1 and mu = 1 take the fast kernels; Ai, p != 1, tau'
 // and the linear-weight test mode take the general ones.
+// L and q of eq:weights_unnormalized (both 0 select the paper's 1, 1)
+inline double weight_L(const za_problem& p) { return p.weight_L == 0.0 && p.weight_q == 0.0 ? 1.0 : p.weight_L; }
+inline double weight_q(const za_problem& p) { return p.weight_L == 0.0 && p.weight_q == 0.0 ? 1.0 : p.weight_q; }
+
 inline bool general_weights(const za_problem& p) {
-  return p.p != 1.0 || p.affine_invariant || p.linear_weights || p.alt_tau;
+  return p.p != 1.0 || p.affine_invariant || p.linear_weights || p.alt_tau || weight_L(p) != 1.0 ||
+         weight_q(p) != 1.0;
 }
 
 template <class T>
@@ -61,6 +66,9 @@ inline za::CfgArg<T> make_cfg(const za_problem& p) {
   c.w.ai = p.affine_invariant;
   c.w.linear = p.linear_weights;
   c.w.alt_tau = p.alt_tau;
+  c.w.L = (T)weight_L(p);
+  c.w.q = (T)weight_q(p);
+  c.w.pq = (T)(p.p * weight_q(p));
   return c;
 }
 

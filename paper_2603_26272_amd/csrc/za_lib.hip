@@ -59,6 +59,8 @@ za_status za_validate(const za_problem* p, std::string* why) {
   if (p->order != 0 && (p->order < 2 || p->order > 5)) return fail("order r must be 2, 3, 4 or 5");
   if (p->pp_limiter != 0 && p->pp_limiter != 1) return fail("pp_limiter must be 0 or 1");
   if (p->alt_tau != 0 && p->alt_tau != 1) return fail("alt_tau must be 0 or 1");
+  if (!(weight_L(*p) >= 0.0) || !(weight_L(*p) < 1e300)) return fail("weight_L must be finite and >= 0");
+  if (!(weight_q(*p) >= 1.0) || !(weight_q(*p) < 1e300)) return fail("weight_q must be finite and >= 1");
   if (p->alt_tau && order_of(*p) != 3) {
     if (why) *why = "the alternative global indicator is defined here for r = 3 only";
     return ZA_ERR_UNSUPPORTED;

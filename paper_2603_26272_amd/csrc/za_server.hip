@@ -98,6 +98,9 @@ __device__ __forceinline__ CfgArg<T> slot_cfg(const SlotDesc& d) {
   c.w.ai = 0;
   c.w.linear = 0;
   c.w.alt_tau = 0;
+  c.w.L = T(1);
+  c.w.q = T(1);
+  c.w.pq = T(1);
   return c;
 }
 
@@ -504,7 +507,7 @@ za_status za_server_submit(za_server* sv, const za_problem* p, const double* q0,
   }
   // batches run the paper's weights (Z type, p = 1, mu = 1) on the Euler equations
   if (p->system != ZA_EULER || p->p != 1.0 || p->affine_invariant || p->linear_weights || order_of(*p) != 3 ||
-      p->pp_limiter || p->alt_tau)
+      p->pp_limiter || p->alt_tau || weight_L(*p) != 1.0 || weight_q(*p) != 1.0)
     return ZA_ERR_UNSUPPORTED;
   int sb, xb, ys, yb;
   if (footprint(*p, &sb, &xb, &ys, &yb) > sv->budget) return ZA_ERR_NOMEM;

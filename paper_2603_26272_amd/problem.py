@@ -46,6 +46,8 @@ class Problem:
     order: int = 3          # r of the order-2r central-upwind scheme (3: WENO-ZA6)
     pp_limiter: int = 0     # 1: positivity-preserving flux limiter in time steps (Euler, FP64)
     alt_tau: int = 0        # 1: the alternative global indicator tau' (eq:GSI_alt; r = 3)
+    weight_L: float = 1.0   # L and q of eq:weights_unnormalized (JS family: L = 0, p = 2)
+    weight_q: float = 1.0
 
     @property
     def m(self) -> int:

@@ -46,6 +46,8 @@ class ZaProblem(C.Structure):
         ("order", C.c_int32),
         ("pp_limiter", C.c_int32),
         ("alt_tau", C.c_int32),
+        ("weight_L", C.c_double),
+        ("weight_q", C.c_double),
     ]
 
     @classmethod
