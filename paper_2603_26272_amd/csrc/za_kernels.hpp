@@ -539,18 +539,26 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
 }
 
 // ---------------------------------------------------------------------------
-// Looped x-sweep of the 2D stage (MODE_LX, FP64 records): one wavefront per
-// row segment of 64 nc - 1 cells, walked in nc chunks of 64 interfaces.  Lane
-// l of chunk j computes interface I0 + l (I0 = s0 + 64 j) from a 128-cell LDS
-// ring of records; each chunk first adds the next 64 cells to the ring (their
-// state was loaded while the previous chunk computed its fluxes) and then
-// completes the partial stage of cell I0 - 1 + l, whose left flux the
-// previous chunk's lane 63 left in a carry slot.  Every record is built once
-// per segment, and neighbouring segments share one interface, so a row of
-// 2048 cells takes the same 33 flux passes as the one-shot sweep with half
-// its record passes.
+// Looped x-sweep of a stage (FP64 records): one wavefront per row segment of
+// 64 nc - 1 cells, walked in nc chunks of 64 interfaces.  Lane l of chunk j
+// computes interface I0 + l (I0 = s0 + 64 j) from a 128-cell LDS ring of
+// records; each chunk first adds the next 64 cells to the ring (their state
+// was loaded while the previous chunk computed its fluxes) and then updates
+// cell I0 - 1 + l, whose left flux the previous chunk's lane 63 left in a
+// carry slot.  Every record is built once per segment, and neighbouring
+// segments share one interface, so a row of 2048 cells takes the same 33 flux
+// passes as the one-shot sweep with half its record passes.
+//   MODE_LX (2D): the partial stage ca Q^n + cb (Q + dt L_x).
+//   MODE_STAGE (1D): the whole RK3 stage, and the wave-speed maxima of the new
+//   states, one row of a.part per wavefront (row = global wavefront index;
+//   the ny * nseg live wavefronts fill rows 0 .. ny * nseg - 1).
 // ---------------------------------------------------------------------------
 constexpr int XL_RING = 128;
+
+// live wavefronts of the looped sweep: ny rows of segments of 64 nc - 1 cells
+__host__ __device__ constexpr long long xl_waves(int nx, int ny, int nc) {
+  return (long long)ny * ((nx + 64LL * nc - 2) / (64LL * nc - 1));
+}
 
 __device__ __forceinline__ int xl_slot(int k) { return k & (XL_RING - 1); }
 
@@ -571,17 +579,32 @@ __device__ __forceinline__ void xl_record(const double (&qp)[M], const Phys& ph,
   }
 }
 
-template <int SYS, int M, int WV>
+// The maxima of a wavefront's lanes to dst[0 .. NPART-1] (lane 0 stores).
+// cell_speeds leaves numbers or +inf, never NaN, so fmax is the exact max.
+__device__ __forceinline__ void wave_max_store(double (&r)[NPART], double* __restrict__ dst) {
+#pragma unroll
+  for (int i = 0; i < NPART; ++i) {
+    for (int off = 32; off > 0; off >>= 1) r[i] = fmax(r[i], __shfl_xor(r[i], off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < NPART; ++i) dst[i] = r[i];
+  }
+}
+
+template <int SYS, int M, int WV, int MODE = MODE_LX>
 __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<double>& cfg, int bid) {
+  static_assert(MODE == MODE_LX || MODE == MODE_STAGE, "the looped sweep writes stage states");
   constexpr int R = 3;
   if (a.check_active && !a.ctl->active) return;
-  const SweepConst sk = sweep_const<0>(a.ctl, a.g, false, true);
+  const SweepConst sk = sweep_const<0>(a.ctl, a.g, false, MODE == MODE_LX);
   constexpr int NF = NumFields<SYS, M>::value;
   __shared__ double xr[4][NF * XL_RING];
   __shared__ double fl[4][M][66];   // [l + 1]: flux of lane l; [65]: carry from the previous chunk
   const int lane = threadIdx.x & 63, wv = wave_id();
   const int nx = a.g.nx, ny = a.g.ny;
   const int nc = a.xl_chunks;
+  if (nc < 1) return;   // launched only with nc >= 1; never index with a negative segment
   const int seg_cells = 64 * nc - 1;
   const int nseg = (nx + seg_cells - 1) / seg_cells;
   const int wid = bid * 4 + wv;
@@ -595,6 +618,9 @@ __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<d
   double(*const fw)[66] = fl[wv];
   const int bcx = a.g.bc_x;
   // ring slot of cell k is (k - s0 + R) mod 128; cells s0 - R .. s0 - R + 63 first
+  double rs[NPART];
+#pragma unroll
+  for (int t = 0; t < NPART; ++t) rs[t] = -__builtin_huge_val();
   double qp[M];
   {
     double q0[M];   // both loads in flight before the first records
@@ -632,6 +658,7 @@ __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<d
     wave_sync();
     if (upd) {
       const int si = xl_slot(64 * j + lane - 1 + R);
+      double qnew[M];
 #pragma unroll
       for (int c = 0; c < M; ++c) {
         double qc;
@@ -644,8 +671,10 @@ __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<d
         }
         const double Fm = lane == 0 ? fw[c][65] : fw[c][lane];
         const double L = -(fw[c][lane + 1] - Fm) * a.g.inv_dx;
-        a.out[c * cs + (size_t)line * nx + i] = fma(a.ca, qb[c], a.cb * fma(sk.dt, L, qc));
+        qnew[c] = fma(a.ca, qb[c], a.cb * fma(sk.dt, L, qc));
+        a.out[c * cs + (size_t)line * nx + i] = qnew[c];
       }
+      if (MODE == MODE_STAGE) cell_speeds<SYS, M>(qnew, a.ph, rs);
     }
     wave_sync();
     if (lane == 63 && I <= nx) {
@@ -653,11 +682,12 @@ __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<d
       for (int c = 0; c < M; ++c) fw[c][65] = fw[c][64];
     }
   }
+  if (MODE == MODE_STAGE && a.part) wave_max_store(rs, a.part + (size_t)wid * NPART);
 }
 
-template <int SYS, int M, int WV>
+template <int SYS, int M, int WV, int MODE = MODE_LX>
 __global__ __launch_bounds__(256, 3) void k_sweep_xl(SweepArgs a, CfgArg<double> cfg) {
-  sweep_xl_body<SYS, M, WV>(a, cfg, blockIdx.x);
+  sweep_xl_body<SYS, M, WV, MODE>(a, cfg, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

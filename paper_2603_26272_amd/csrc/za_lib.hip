@@ -154,11 +154,14 @@ static void launch_x_t(za_ctx* c, int mode, const SweepArgs& a) {
       return;
     }
   }
-  if constexpr (sizeof(T) == sizeof(double) && WV == WV_Z1 && (SYS != SYS_EULER || M == 4)) {
-    if (mode == MODE_LX && a.xl_chunks > 0) {
-      const int seg_cells = 64 * a.xl_chunks - 1;
-      const long long w = (long long)a.g.ny * ((a.g.nx + seg_cells - 1) / seg_cells);
-      hipLaunchKernelGGL((k_sweep_xl<SYS, M, WV>), dim3((unsigned)((w + 3) / 4)), blk, 0, c->stream, a, cfg);
+  if constexpr (sizeof(T) == sizeof(double) && WV == WV_Z1) {
+    if ((mode == MODE_LX || mode == MODE_STAGE) && a.xl_chunks > 0) {
+      const long long w = xl_waves(a.g.nx, a.g.ny, a.xl_chunks);
+      const dim3 gl((unsigned)((w + 3) / 4));
+      if (mode == MODE_LX)
+        hipLaunchKernelGGL((k_sweep_xl<SYS, M, WV, MODE_LX>), gl, blk, 0, c->stream, a, cfg);
+      else
+        hipLaunchKernelGGL((k_sweep_xl<SYS, M, WV, MODE_STAGE>), gl, blk, 0, c->stream, a, cfg);
       return;
     }
   }
@@ -343,7 +346,7 @@ static int pick_ytile(za_ctx* c) {
   return std::max(rows, YS_TILE_MIN);
 }
 
-// Chunks per row segment of the looped x-sweep (2D stages, FP64, r = 3, Z
+// Chunks per row segment of the looped x-sweep (stages in FP64, r = 3, Z
 // weights with p = 1, no limiter; 0: the one-shot sweep).  A wavefront walks nc chunks of 64
 // interfaces; the choice minimises rounds of resident wavefronts x chunks
 // per wavefront (a record pass counted as 1/32 of a flux pass), i.e. the
@@ -351,14 +354,15 @@ static int pick_ytile(za_ctx* c) {
 // ZA_XL_CHUNKS in the environment forces a value (0 disables the sweep).
 static int pick_xl_chunks(za_ctx* c) {
   const za_problem& p = c->prob;
-  if (p.dim != 2 || p.precision != ZA_FP64 || order_of(p) != 3 || p.pp_limiter || general_weights(p)) return 0;
+  if (p.precision != ZA_FP64 || order_of(p) != 3 || p.pp_limiter || general_weights(p)) return 0;
   if (const char* e = std::getenv("ZA_XL_CHUNKS")) {
     const int v = std::atoi(e);
     return v < 0 ? 0 : std::min(v, 256);
   }
   int blocks_per_cu = 0, cus = 0;
-  const void* fn = p.system == ZA_EULER ? reinterpret_cast<const void*>(&k_sweep_xl<SYS_EULER, 4, WV_Z1>)
-                                        : reinterpret_cast<const void*>(&k_sweep_xl<SYS_ADV, 1, WV_Z1>);
+  const void* fn = p.system != ZA_EULER ? reinterpret_cast<const void*>(&k_sweep_xl<SYS_ADV, 1, WV_Z1, MODE_LX>)
+                   : p.dim == 2         ? reinterpret_cast<const void*>(&k_sweep_xl<SYS_EULER, 4, WV_Z1, MODE_LX>)
+                                        : reinterpret_cast<const void*>(&k_sweep_xl<SYS_EULER, 3, WV_Z1, MODE_STAGE>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, fn, 256, 0) != hipSuccess || blocks_per_cu < 1)
     blocks_per_cu = 3;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
@@ -368,7 +372,7 @@ static int pick_xl_chunks(za_ctx* c) {
   long long best_cost = -1;
   for (int nc = 1; nc <= 64; ++nc) {
     const long long seg = 64LL * nc - 1;
-    const long long waves = (long long)p.ny * ((p.nx + seg - 1) / seg);
+    const long long waves = xl_waves(p.nx, p.ny, nc);
     const long long cost = ((waves + slots - 1) / slots) * (32LL * nc + nc + 1);
     if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = nc; }
     if (seg >= p.nx) break;   // one segment per row from here on
@@ -524,6 +528,8 @@ za_status za_ctx_create(const za_problem* p, void* stream, za_ctx** out) {
   c->xl_chunks = pick_xl_chunks(c);
   if (p->dim == 2) {
     c->stage_blocks = ((p->nx + 63) / 64) * ((p->ny + c->ytile - 1) / c->ytile);
+  } else if (c->xl_chunks > 0) {   // one row of maxima per wavefront of the looped sweep
+    c->stage_blocks = (int)xl_waves(p->nx, p->ny, c->xl_chunks);
   } else {
     const long long nseg = (p->nx + XS_CELLS - 1) / XS_CELLS;
     c->stage_blocks = (int)((nseg * p->ny + 3) / 4);

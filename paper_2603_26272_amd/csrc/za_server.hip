@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <limits>
@@ -51,7 +52,8 @@ struct SlotDesc {
   int xblocks;       // x-sweep blocks
   int ystrips;       // y-sweep: 64-column strips
   int yblocks;       // y-sweep blocks (strips x tiles)
-  int stage_blocks;  // blocks of the kernel that writes a stage state
+  int stage_blocks;  // rows of wave-speed maxima the kernel that writes a stage state leaves
+  int xl_chunks;     // FP64: chunks per segment of the looped x-sweep
 };
 
 struct BatchTable {
@@ -84,7 +86,7 @@ __device__ __forceinline__ SweepArgs slot_args(const SlotDesc& d, int stage, boo
   a.check_active = 1;
   a.ytile = SERVE_YTILE;
   a.part = d.part;
-  a.xl_chunks = 0;
+  a.xl_chunks = d.xl_chunks;
   return a;
 }
 
@@ -119,6 +121,19 @@ __global__ __launch_bounds__(256, ZA_SRV_XS_WAVES) void kb_sweep_x(const BatchTa
     sweep_x_body<SYS_EULER, M, T, MODE_LX, WV_Z1>(a, cfg, b - tab->xoff[s]);
   else
     sweep_x_body<SYS_EULER, M, T, MODE_STAGE, WV_Z1>(a, cfg, b - tab->xoff[s]);
+}
+
+// FP64 classes: the looped x-sweep (2D: partial stage; 1D: the whole stage
+// and one row of wave-speed maxima per wavefront).
+template <int M>
+__global__ __launch_bounds__(256, 3) void kb_sweep_xl(const BatchTable* __restrict__ tab, int stage) {
+  const int b = blockIdx.x;
+  if (b >= tab->xtot) return;
+  const int s = find_slot(tab->xoff, tab->n, b);
+  const SlotDesc& d = tab->s[s];
+  const SweepArgs a = slot_args(d, stage, M == 4);
+  const CfgArg<double> cfg = slot_cfg<double>(d);
+  sweep_xl_body<SYS_EULER, M, WV_Z1, M == 4 ? MODE_LX : MODE_STAGE>(a, cfg, b - tab->xoff[s]);
 }
 
 template <class T>
@@ -207,7 +222,15 @@ struct Req {
   size_t off = 0, bytes = 0;
   SlotDesc desc;
   int64_t steps = 0, interfaces = 0;
+  int64_t launched = 0;    // RK3 steps enqueued since admission
 };
+
+// RK3 steps a class runs between two synchronisations of the scheduler: as
+// many as the active request closest to its step count still needs (so no
+// request finishes later than with one step per pass and no launched step
+// is idle for all of them), at most SERVE_MAX_BURST (new arrivals wait at
+// most that many steps for admission).
+constexpr int SERVE_MAX_BURST = 8;
 
 static int class_of(const za_problem& p) { return (p.dim == 2 ? 2 : 0) + (p.precision == ZA_FP32_RECON ? 1 : 0); }
 static int ncomp(const za_problem& p) { return p.dim == 1 ? 3 : 4; }
@@ -253,11 +276,26 @@ struct za_server {
   std::string err;
 };
 
-static size_t footprint(const za_problem& p, int* stage_blocks, int* xblocks, int* ystrips, int* yblocks) {
+// Chunks per segment of the looped x-sweep, which FP64 requests always use
+// (0 for FP32 reconstruction: the one-shot sweep), fixed at admission (its
+// wave-speed rows depend on it in 1D): segments of about a quarter row in 2D
+// and of up to 4 chunks in 1D keep many wavefronts per request.
+// ZA_SRV_XL_CHUNKS in the environment forces a value, clamped to 1 .. 64.
+static int serve_xl_chunks(const za_problem& p) {
+  if (p.precision != ZA_FP64) return 0;
+  if (const char* e = std::getenv("ZA_SRV_XL_CHUNKS")) return std::max(1, std::min(std::atoi(e), 64));
+  const int nc = p.dim == 2 ? p.nx / 256 : p.nx / 2048;
+  return std::max(1, std::min(4, nc));
+}
+
+static size_t footprint(const za_problem& p, int* stage_blocks, int* xblocks, int* ystrips, int* yblocks,
+                        int* xl_chunks) {
   const int m = ncomp(p);
   const size_t S = (size_t)m * p.nx * p.ny * sizeof(double);
-  const long long nseg = (p.nx + XS_CELLS - 1) / XS_CELLS;
-  *xblocks = (int)((nseg * p.ny + 3) / 4);
+  *xl_chunks = serve_xl_chunks(p);
+  const long long xw = *xl_chunks > 0 ? xl_waves(p.nx, p.ny, *xl_chunks)
+                                      : (long long)p.ny * ((p.nx + XS_CELLS - 1) / XS_CELLS);
+  *xblocks = (int)((xw + 3) / 4);
   if (p.dim == 2) {
     *ystrips = (p.nx + 63) / 64;
     *yblocks = *ystrips * ((p.ny + SERVE_YTILE - 1) / SERVE_YTILE);
@@ -265,7 +303,7 @@ static size_t footprint(const za_problem& p, int* stage_blocks, int* xblocks, in
   } else {
     *ystrips = 0;
     *yblocks = 0;
-    *stage_blocks = *xblocks;
+    *stage_blocks = *xl_chunks > 0 ? (int)xw : *xblocks;
   }
   const size_t part = ((size_t)*stage_blocks * NPART * sizeof(double) + 255) & ~size_t(255);
   return (p.dim == 2 ? 4 : 3) * ((S + 255) & ~size_t(255)) + part;
@@ -296,14 +334,14 @@ static hipError_t class_step(za_server* sv, int c) {
           hipLaunchKernelGGL((kb_sweep_x<4, float>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
           hipLaunchKernelGGL((kb_sweep_y<float>), dim3(key.ycap), dim3(256), 0, C.stream, C.dtab, s);
         } else {
-          hipLaunchKernelGGL((kb_sweep_x<4, double>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
+          hipLaunchKernelGGL((kb_sweep_xl<4>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
           hipLaunchKernelGGL((kb_sweep_y<double>), dim3(key.ycap), dim3(256), 0, C.stream, C.dtab, s);
         }
       } else {
         if (fp32)
           hipLaunchKernelGGL((kb_sweep_x<3, float>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
         else
-          hipLaunchKernelGGL((kb_sweep_x<3, double>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
+          hipLaunchKernelGGL((kb_sweep_xl<3>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
       }
     }
     hipLaunchKernelGGL(kb_step_end, dim3(key.ncap), dim3(64), 0, C.stream, C.dtab);
@@ -345,8 +383,8 @@ static void admit(za_server* sv) {
     Class& C = sv->cls[r->cls];
     if (total >= sv->max_slots) break;
     if (C.free_slots.empty()) { ++it; continue; }
-    int sb, xb, ys, yb;
-    const size_t need = footprint(r->prob, &sb, &xb, &ys, &yb);
+    int sb, xb, ys, yb, xc;
+    const size_t need = footprint(r->prob, &sb, &xb, &ys, &yb, &xc);
     size_t off;
     if (!sv->pool.alloc(need, &off)) { ++it; continue; }
     r->off = off;
@@ -374,7 +412,7 @@ static void admit(za_server* sv) {
     d.ph.cfl = p.cfl; d.ph.dt_rule = p.dt_rule; d.ph.lf_scalar = p.lf == ZA_LF_SCALAR ? 1 : 0;
     d.ph.pp = 0;   // requests with the limiter are not admitted
     d.eps16 = 16.0 * p.eps; d.eps4 = 4.0 * p.eps; d.mu0x2 = 2.0 * p.mu0;
-    d.xblocks = xb; d.ystrips = ys; d.yblocks = yb; d.stage_blocks = sb;
+    d.xblocks = xb; d.ystrips = ys; d.yblocks = yb; d.stage_blocks = sb; d.xl_chunks = xc;
     // upload, control block, and the wave speeds of Q^0
     (void)hipMemcpyAsync(d.st, r->q0.data(), r->m * r->ncell * sizeof(double), hipMemcpyHostToDevice, C.stream);
     DevCtl v;
@@ -414,7 +452,7 @@ static void scheduler(za_server* sv) {
       sv->cv_work.wait(lk, [&] { return sv->stop || !sv->waiting.empty(); });
       continue;
     }
-    // table uploads and one RK3 step per class (streams overlap)
+    // table uploads and a burst of RK3 steps per class (streams overlap)
     for (int c = 0; c < NCLASS; ++c) {
       Class& C = sv->cls[c];
       if (C.active.empty()) continue;
@@ -423,7 +461,12 @@ static void scheduler(za_server* sv) {
         (void)hipMemcpyAsync(C.dtab, C.htab, sizeof(BatchTable), hipMemcpyHostToDevice, C.stream);
         C.dirty = false;
       }
-      if (class_step(sv, c) != hipSuccess) sv->err = "graph launch failed";
+      int64_t burst = SERVE_MAX_BURST;
+      for (const Req* r : C.active) burst = std::min(burst, r->n_steps - r->launched);
+      burst = std::max<int64_t>(burst, 1);
+      for (int64_t k = 0; k < burst; ++k)
+        if (class_step(sv, c) != hipSuccess) sv->err = "graph launch failed";
+      for (Req* r : C.active) r->launched += burst;
       (void)hipMemcpyAsync(C.hctl, C.dctl, MAX_SLOTS * sizeof(DevCtl), hipMemcpyDeviceToHost, C.stream);
     }
     lk.unlock();
@@ -509,8 +552,8 @@ za_status za_server_submit(za_server* sv, const za_problem* p, const double* q0,
   if (p->system != ZA_EULER || p->p != 1.0 || p->affine_invariant || p->linear_weights || order_of(*p) != 3 ||
       p->pp_limiter || p->alt_tau || weight_L(*p) != 1.0 || weight_q(*p) != 1.0)
     return ZA_ERR_UNSUPPORTED;
-  int sb, xb, ys, yb;
-  if (footprint(*p, &sb, &xb, &ys, &yb) > sv->budget) return ZA_ERR_NOMEM;
+  int sb, xb, ys, yb, xc;
+  if (footprint(*p, &sb, &xb, &ys, &yb, &xc) > sv->budget) return ZA_ERR_NOMEM;
   auto r = std::make_unique<Req>();
   r->prob = *p;
   r->cls = class_of(*p);

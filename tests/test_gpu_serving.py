@@ -108,3 +108,23 @@ def test_failing_request_is_isolated(dev):
     for i, j in ((0, 0), (1, 1), (3, 2)):
         assert res[i][0] == 0
         assert np.array_equal(res[i][1], serve([good[j]])[0][1])
+
+
+def test_served_chunk_counts_bitwise(dev, monkeypatch):
+    """FP64 requests use the looped x-sweep (segments of 64 nc - 1 cells; in
+    1D it also leaves the wave speeds, one row per wavefront).
+    ZA_SRV_XL_CHUNKS forces nc at admission (clamped to 1 .. 64); every
+    choice gives the states of the single context path's one-shot sweep
+    bitwise."""
+    reqs = [(*W.riemann_1d(5, 5000), 12), (*W.quadrants_2d(6, 700, 90), 12), (*W.riemann_1d(8, 300), 12),
+            (*W.quadrants_2d(9, 65, 130), 12)]
+    monkeypatch.setenv("ZA_XL_CHUNKS", "0")
+    ref = [ctx_solve(P, q0, n, dev) for P, q0, n in reqs]
+    monkeypatch.delenv("ZA_XL_CHUNKS")
+    for nc in (0, 1, 3, 7):
+        monkeypatch.setenv("ZA_SRV_XL_CHUNKS", str(nc))
+        res = serve(reqs)
+        for i, (st, q, stats) in enumerate(res):
+            assert st == 0 and stats["steps"] == 12, (nc, i, st)
+            assert np.array_equal(q, ref[i]), (nc, i)
+    monkeypatch.delenv("ZA_SRV_XL_CHUNKS")
