@@ -117,7 +117,11 @@ typedef struct {
   int64_t nonfinite_step;  /* first step whose input was non-finite, else -1  */
 } za_solve_info;
 
-/* Create a context for one problem shape on the current HIP device.
+/* Create a context for one problem shape on the current HIP device: the
+ * conservation law, mesh, initial-boundary setting and scheme parameters of
+ * the paper's problem statement (Section 2, eq:hyperbolic_1D_scalar; the
+ * Euler systems eq:Euler1D and Section 4.3; eps and p of
+ * eq:weight_nonlinear, Section 4).
  * hip_stream: a hipStream_t (NULL = the default stream).  Allocates the
  * workspace (two RK3 stage states, the x-sweep partial RHS in 2D, the
  * reduction partials and a device control block).  *out receives the
@@ -126,12 +130,17 @@ typedef struct {
  * 64 interfaces per row segment of the looped 2D x-sweep (0: one-shot
  * sweep; results are identical either way). */
 za_status za_ctx_create(const za_problem* problem, void* hip_stream, za_ctx** out);
+/* Not from the paper (resource management): synchronise the context's
+ * stream, free its workspace and the context.  ZA_ERR_ARG for NULL. */
 za_status za_ctx_destroy(za_ctx* ctx);
-/* Rebind the stream used by later calls. */
+/* Not from the paper (stream plumbing): rebind the stream used by later
+ * calls.  ZA_ERR_ARG for NULL. */
 za_status za_ctx_set_stream(za_ctx* ctx, void* hip_stream);
-/* Number of doubles in one state: m * nx * ny. */
+/* Number of doubles in one state: m * nx * ny, the point values Q_i of
+ * eq:hyperbolic_1D_scalar_h (0 if the problem is invalid). */
 size_t    za_state_count(const za_problem* problem);
-/* Device bytes the context allocates for this problem (admission control). */
+/* Not from the paper (admission control): device bytes the context
+ * allocates for this problem (0 if the problem is invalid). */
 size_t    za_workspace_bytes(const za_problem* problem);
 
 /* rhs = L(q) = -(F_{i+1/2} - F_{i-1/2})/dx [- (G_{j+1/2} - G_{j-1/2})/dy]
@@ -140,40 +149,61 @@ size_t    za_workspace_bytes(const za_problem* problem);
  * doubles, must not overlap. */
 za_status za_rhs(za_ctx* ctx, const double* q, double* rhs);
 
-/* The WENO-ZA6 numerical fluxes themselves (parity checks): fx[c][y][k] is
- * F at x_{k-1/2}, k = 0..nx (size m*ny*(nx+1)); fy[c][k][x] is G at
- * y_{k-1/2}, k = 0..ny (size m*(ny+1)*nx; 2D only, may be NULL). */
+/* The numerical fluxes themselves (parity checks): h_{i+1/2} = f^+ + f^-
+ * of the global Lax-Friedrichs splitting eq:LF, each half the convex
+ * combination eq:numerical_flux_WENO of the candidate fluxes
+ * eq:numerical_subflux with the weights eq:weights_general; for the Euler
+ * equations per characteristic field (Section 4.2).  fx[c][y][k] is F at
+ * x_{k-1/2}, k = 0..nx (device, m*ny*(nx+1) doubles); fy[c][k][x] is G at
+ * y_{k-1/2}, k = 0..ny (device, m*(ny+1)*nx doubles; 2D only, may be NULL).
+ * Asynchronous; ZA_ERR_ARG for NULL q or fx. */
 za_status za_rhs_fluxes(za_ctx* ctx, const double* q, double* fx, double* fy);
 
-/* One SSP-RK3 step in place (Shu-Osher form).  dt > 0: that step; dt <= 0:
- * the CFL step of the problem's dt rule from q.  dt_used (host, may be NULL):
- * if given, the call synchronises and stores the dt taken. */
+/* One step of the explicit third-order TVD Runge-Kutta method of Shu and
+ * Osher (Section 4, opening paragraph) in place, in its Shu-Osher form
+ * Q1 = Q + dt L(Q), Q2 = 3/4 Q + 1/4 (Q1 + dt L(Q1)),
+ * Q <- 1/3 Q + 2/3 (Q2 + dt L(Q2)), with L of eq:hyperbolic_1D_scalar_h.
+ * q: device state, updated in place.  dt > 0: that step; dt <= 0: the CFL
+ * step of the problem's dt rule from q.  dt_used (host, may be NULL): if
+ * given, the call synchronises and stores the dt taken (and reports
+ * ZA_ERR_NONFINITE for a non-physical state). */
 za_status za_step(za_ctx* ctx, double* q, double dt, double* dt_used);
 
-/* Integrate q in place.  t_final > 0: to t_final, the last step clipped to
- * land on it (ZA_DT_CFL_H2: n = ceil(T/dt (1 - 1e-12)) equal steps, the
+/* Integrate q in place to the final time of an experiment (Section 4: every
+ * test runs the TVD Runge-Kutta steps of za_step from t = 0 to its final
+ * time T, e.g. T = 0.8 for configuration 3 of Section 4.3) with the CFL
+ * rule recomputed each step.  t_final > 0: to t_final, the last step
+ * clipped to land on it (ZA_DT_CFL_H2: n = ceil(T/dt (1 - 1e-12)) equal steps, the
  * last T - (n-1) dt), stopping early after max_steps if max_steps > 0.
  * t_final <= 0: exactly max_steps CFL steps without clipping.  dt and t stay
  * on the device; the host checks progress once per captured chunk of steps.
  * info (host, may be NULL) receives the step statistics.  Synchronises. */
 za_status za_solve(za_ctx* ctx, double* q, double t_final, int64_t max_steps, za_solve_info* info);
 
-/* FP64 totals of each conserved variable (fixed-order tree, so repeatable
- * bit for bit): sums[c] = sum over cells of q[c].  sums: host, m doubles.
+/* FP64 totals of each conserved variable, sums[c] = sum over cells of q[c]
+ * (the conservative form eq:hyperbolic_1D_scalar_h telescopes, so with
+ * periodic boundaries these stay constant up to rounding).  Fixed-order
+ * tree, repeatable bit for bit.  q: device; sums: host, m doubles.
  * Synchronises. */
 za_status za_conserved_sums(za_ctx* ctx, const double* q, double* sums);
 
+/* Not from the paper (diagnostics): a static string naming a status, and
+ * the last error message of a context (owned by the context). */
 const char* za_status_str(za_status s);
 const char* za_ctx_last_error(const za_ctx* ctx);
-/* Per-launch device time (ms) of the most recent za_rhs/za_step/za_solve
- * kernels, by kernel class, when timing is enabled (see za_ctx_set_timing):
+/* Not from the paper (measurement): per-launch device time (ms) of the most
+ * recent za_rhs/za_step/za_solve kernels, by kernel class, when timing is
+ * enabled (za_ctx_set_timing; timing records events around every launch and
+ * runs steps without the captured step graphs):
  * out[0] = x-sweep, out[1] = y-sweep(+stage), out[2] = wave-speed reduction;
- * counts[k] = number of launches averaged. */
+ * counts[k] = number of launches averaged.  Synchronises. */
 za_status za_ctx_set_timing(za_ctx* ctx, int32_t enable);
 za_status za_ctx_kernel_times(za_ctx* ctx, double* avg_ms, int64_t* counts);
 
 /* ---------------------------------------------------------------------- */
-/* Serving: continuous batching of independent solve requests.             */
+/* Serving (not from the paper, which solves one problem at a time): each  */
+/* request is a za_solve of its own problem (the paper's method, as above); */
+/* the server adds continuous batching of independent solve requests.      */
 /* Requests are admitted while their device footprint fits the HBM budget */
 /* and a slot is free; every scheduler step advances all admitted requests */
 /* by one RK3 step with batched launches (one launch per kernel class for  */
@@ -189,20 +219,27 @@ typedef struct {
   int32_t status;                            /* za_status of the request    */
 } za_req_stats;
 
-/* hbm_budget_bytes: cap on the summed footprint of admitted requests.
- * max_slots: concurrent requests.  device: HIP device ordinal. */
+/* Not from the paper.  hbm_budget_bytes: cap on the summed footprint of
+ * admitted requests (the server allocates one pool of that size).
+ * max_slots: concurrent requests.  device: HIP device ordinal.  *out
+ * receives the server (NULL on error). */
 za_status za_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t device, za_server** out);
-/* Copies q0_host (m*nx*ny doubles) and queues the request for n_steps CFL
- * steps.  ZA_ERR_NOMEM if its footprint exceeds the whole budget. */
+/* Not from the paper.  Copies q0_host (host, m*nx*ny doubles) and queues
+ * the request for n_steps CFL steps (za_step's method).  ZA_ERR_NOMEM if
+ * its footprint exceeds the whole budget; ZA_ERR_ARG for an invalid
+ * problem or a configuration the server does not run. */
 za_status za_server_submit(za_server* s, const za_problem* problem, const double* q0_host,
                            int64_t n_steps, za_req_id* id);
-/* done = 1 once finished; then q_out_host (may be NULL) receives the final
- * state and stats (may be NULL) the request's record.  The request is
- * released after a successful poll with done = 1 and q_out_host != NULL. */
+/* Not from the paper.  done = 1 once finished; then q_out_host (host, may
+ * be NULL) receives the final state and stats (may be NULL) the request's
+ * record.  The request is released after a successful poll with done = 1
+ * and q_out_host != NULL. */
 za_status za_server_poll(za_server* s, za_req_id id, int32_t* done, double* q_out_host,
                          za_req_stats* stats);
-/* Block until every submitted request has finished. */
+/* Not from the paper.  Block until every submitted request has finished
+ * (or failed). */
 za_status za_server_drain(za_server* s);
+/* Not from the paper.  Stop the scheduler, free the pool and the server. */
 za_status za_server_destroy(za_server* s);
 
 #ifdef __cplusplus

@@ -91,6 +91,8 @@ def lib():
         L.orc_euler_eigen.restype = None
         L.orc_euler_eigen.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                       C.c_double, C.c_double, _DP, _DP]
+        L.orc_roe_state.restype = None
+        L.orc_roe_state.argtypes = [C.c_int, C.c_double, _DP, _DP, _DP]
         L.orc_set_order_tables.restype = C.c_int
         L.orc_set_order_tables.argtypes = [C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int]
         L.orc_recon_lq.restype = C.c_double
@@ -337,6 +339,16 @@ def count_ops(pb, q, dir_mask=3):
     cnt = (C.c_int64 * 5)()
     nir = lib().orc_count_ops(C.byref(P), _ptr(q), int(dir_mask), cnt)
     return nir, {"add": cnt[0], "mul": cnt[1], "div": cnt[2], "sqrt": cnt[3], "other": cnt[4]}
+
+
+def roe_state(m, gamma, QL, QR):
+    """(u~, v~, H~, c~): the Roe-averaged state of cells QL, QR (conserved
+    variables, m = 3 or 4) that the interface fluxes project with."""
+    ql = np.ascontiguousarray(QL, dtype=np.float64)
+    qr = np.ascontiguousarray(QR, dtype=np.float64)
+    out = np.zeros(4)
+    lib().orc_roe_state(int(m), float(gamma), _ptr(ql), _ptr(qr), _ptr(out))
+    return tuple(float(x) for x in out)
 
 
 def euler_eigen(m, direction, gamma, u, v, H, c):

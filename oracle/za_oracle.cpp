@@ -575,6 +575,34 @@ static void euler_eigen(int m, int dir, R gm1, R u, R v, R H, R c, R* Rm, R* Lm)
   }
 }
 
+/* Roe-averaged interface state of two neighbouring cells L, R (the state
+ * whose eigenvectors the characteristic-wise splitting of Section 4.2 uses;
+ * the paper does not name the average, Roe's is the standard one):
+ *   w_L = sqrt(rho_L) / (sqrt(rho_L) + sqrt(rho_R)),  w_R = 1 - w_L (formed
+ *   as sqrt(rho_R) / (..)),  u~ = w_L u_L + w_R u_R (also v~ and the total
+ *   enthalpy H~ = (E + p)/rho),  c~^2 = (gamma-1)(H~ - |u~|^2/2).
+ * For this state A(Q~) (Q_R - Q_L) = F(Q_R) - F(Q_L) holds exactly, in both
+ * directions of a 2D sweep, which the tests check. */
+template <class R>
+static void roe_state(int m, R gm1, const R* QL, const R* QR, R* u_out, R* v_out, R* H_out, R* c_out) {
+  const R h = R(0.5);
+  R rl = QL[0], rr = QR[0];
+  R ul = QL[1] / rl, ur = QR[1] / rr;
+  R vl = m == 4 ? QL[2] / rl : R(0), vr = m == 4 ? QR[2] / rr : R(0);
+  R pl = gm1 * (QL[m - 1] - h * rl * (ul * ul + vl * vl));
+  R pr = gm1 * (QR[m - 1] - h * rr * (ur * ur + vr * vr));
+  R Hl = (QL[m - 1] + pl) / rl, Hr = (QR[m - 1] + pr) / rr;
+  R sl = r_sqrt(rl), sr = r_sqrt(rr);
+  R wl = sl / (sl + sr), wr = sr / (sl + sr);
+  R u = wl * ul + wr * ur;
+  R v = wl * vl + wr * vr;
+  R H = wl * Hl + wr * Hr;
+  R q2 = m == 4 ? h * (u * u + v * v) : h * (u * u);
+  R c2 = gm1 * (H - q2);
+  *u_out = u; *v_out = v; *H_out = H;
+  *c_out = r_sqrt(c2);
+}
+
 /* Wave speeds of one sweep direction over the interior cells, in FP64:
  * alpha[s] = max |lambda_s| (s over the m characteristic fields) and
  * smax = max(|u_n| + c).  Returns 0 if the state is finite and physical,
@@ -703,22 +731,8 @@ static void line_fluxes(const orc_problem& P, const Scheme<R>& S, const ReconPar
      * F onto the characteristic fields, split and reconstruct each field,
      * project back. */
     const R gm1 = R(P.gamma - 1);
-    const R* QL = &Qc[(size_t)(k - 1 + r) * m];
-    const R* QR = &Qc[(size_t)(k + r) * m];
-    R rl = QL[0], rr = QR[0];
-    R ul = QL[1] / rl, ur = QR[1] / rr;
-    R vl = m == 4 ? QL[2] / rl : R(0), vr = m == 4 ? QR[2] / rr : R(0);
-    R pl = gm1 * (QL[m - 1] - h * rl * (ul * ul + vl * vl));
-    R pr = gm1 * (QR[m - 1] - h * rr * (ur * ur + vr * vr));
-    R Hl = (QL[m - 1] + pl) / rl, Hr = (QR[m - 1] + pr) / rr;
-    R sl = r_sqrt(rl), sr = r_sqrt(rr);
-    R wl = sl / (sl + sr), wr = sr / (sl + sr);
-    R u = wl * ul + wr * ur;
-    R v = wl * vl + wr * vr;
-    R H = wl * Hl + wr * Hr;
-    R q2 = m == 4 ? h * (u * u + v * v) : h * (u * u);
-    R c2 = gm1 * (H - q2);
-    R c = r_sqrt(c2);
+    R u, v, H, c;
+    roe_state<R>(m, gm1, &Qc[(size_t)(k - 1 + r) * m], &Qc[(size_t)(k + r) * m], &u, &v, &H, &c);
     R Rm[16], Lm[16];
     euler_eigen<R>(m, dir, gm1, u, v, H, c, Rm, Lm);
     R W[2 * R_MAX][4], G[2 * R_MAX][4];
@@ -1092,6 +1106,15 @@ void orc_euler_eigen(int m, int dir, double gamma, double u, double v, double H,
 }
 
 int orc_ncomp(const orc_problem* p) { return ncomp(*p); }
+
+/* The Roe-averaged interface state (u~, v~, H~, c~) of two cells, as the
+ * interface fluxes use it (m = 3: 1D, v~ = 0; m = 4: 2D, either sweep
+ * direction, since the average does not depend on it). */
+void orc_roe_state(int m, double gamma, const double* QL, const double* QR, double* out4) {
+  double u, v, H, c;
+  roe_state<double>(m, gamma - 1.0, QL, QR, &u, &v, &H, &c);
+  out4[0] = u; out4[1] = v; out4[2] = H; out4[3] = c;
+}
 
 int orc_wave_speeds(const orc_problem* p, const double* q, double* alpha /*[2][4]*/, double* smax /*[2]*/) {
   Ctx C; if (make_ctx(p, &C)) return 1;

@@ -16,7 +16,8 @@ INC = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libza.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["za_lib.hip", "za_server.hip", "za_order.hip"]
+# every translation unit of the library: the HIP sources in csrc/
+SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
 ARCH = os.environ.get("ZA_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INC, "-I", CSRC,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]

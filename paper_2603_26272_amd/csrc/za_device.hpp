@@ -430,10 +430,12 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
   // P = q2 Q0 - (u Q1 + v Q2 - E) and D = u Q0 - Q1 the left eigenvectors
   // give w_0 = (b1/2) P + D/(2c), w_3 = (b1/2) P - D/(2c), w_1 = Q0 - b1 P;
   // the acoustic fields 0 and M-1 are carried scaled by 2c, as
-  // (gm1/c) P +- D.  The reconstruction commutes with a constant scale of a
-  // field (its weights are scale-invariant; epsilon aside, which only
-  // matters where a field is flat to 1e-20), so the factor 1/(2c) is
-  // applied to the reconstructed fluxes instead: one FMA per value here.
+  // (gm1/c) P +- D, and the factor 1/(2c) is applied to the reconstructed
+  // fluxes instead: one FMA per value here.  The reconstruction of a field
+  // scaled by s equals s times the reconstruction of the field when the
+  // indicators' epsilon is scaled by s^2 (beta and tau scale by s^2) and the
+  // descaler's mu_0 by s (mu scales by s), so those two fields take
+  // epsilon 4 c^2 eps and mu_0 2 c mu_0 (eq:weight_nonlinear, eq:aimu).
   T W[M][2 * R], G[M][2 * R];
 #pragma unroll
   for (int j = 0; j < 2 * R; ++j) {
@@ -464,9 +466,18 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
     }
   }
 #undef ZA_R
+  WeightCfg<T> cfg_ac = cfg;
+  if (WV == WV_GENERAL && cfg.ai) {
+    cfg_ac.mu0x2 = cfg.mu0x2 * (c + c);
+  } else {
+    const T s2 = T(4) * c2;
+    cfg_ac.eps16 = cfg.eps16 * s2;
+    cfg_ac.eps4 = cfg.eps4 * s2;
+  }
   T gh[M];
 #pragma unroll
-  for (int s = 0; s < M; ++s) gh[s] = split_pair<T, WV, R>(W[s], G[s], alpha[s], cfg);
+  for (int s = 0; s < M; ++s)
+    gh[s] = split_pair<T, WV, R>(W[s], G[s], alpha[s], (s == 0 || s == M - 1) ? cfg_ac : cfg);
   // back-projection F = R g, the acoustic fluxes unscaled by 1/(2c):
   // gh_0 + gh_3 = (gh'_0 + gh'_3)/(2c), c (gh_3 - gh_0) = (gh'_3 - gh'_0)/2
   const T s03 = (gh[0] + gh[M - 1]) * (T(0.5) * ic);

@@ -77,3 +77,13 @@ inline za::CfgArg<T> make_cfg(const za_problem& p) {
 void launch_x_order(za_ctx* c, int mode, const za::SweepArgs& a);
 void launch_y_order(za_ctx* c, int mode, const za::SweepArgs& a);
 int order_y_blocks_per_cu(const za_problem& p);
+
+// Host-side building blocks of the right-hand side (za_lib.hip), shared with
+// other entry points of the library.
+void init_shape(za_ctx* c, const za_problem* p, hipStream_t stream);
+za::SweepArgs base_args(za_ctx* c);
+void launch_wave(za_ctx* c, const double* q, int kind, int check_active);
+void launch_x(za_ctx* c, int mode, const za::SweepArgs& a);
+void launch_y(za_ctx* c, int mode, const za::SweepArgs& a);
+// reset the control block c->ctl on c->stream (a kernel, no memset)
+void launch_ctl_reset(za_ctx* c);

@@ -94,23 +94,33 @@ constexpr int RED_BLOCKS_MAX = 1024;
 
 __device__ __forceinline__ double wave_max(double a, double b) { return a > b ? a : b; }
 
+// Velocities and sound speed of one Euler cell, each operation rounded once
+// in the order u = m_x / rho, v = m_y / rho,
+// p = (gamma-1) (E - (rho/2) (u^2 + v^2)), c^2 = gamma p / rho, c = sqrt(c^2),
+// with IEEE division and square root and no contraction: the wave speeds,
+// hence the Lax-Friedrichs speeds of eq:LF and the CFL step, are then exact
+// functions of the state that any other correctly rounded evaluation in this
+// order reproduces bit for bit.  Runs once per cell and stage.
+__device__ __forceinline__ void euler_cell_speed(double rho, double mx, double my, double E, const Phys& ph,
+                                                 double& u, double& v, double& p, double& c2) {
+#pragma clang fp contract(off)
+  u = mx / rho;
+  v = my / rho;
+  p = ph.gm1 * (E - 0.5 * rho * (u * u + v * v));
+  c2 = ph.gamma * p / rho;
+}
+
 template <int SYS, int M>
 __device__ __forceinline__ void cell_speeds(const double (&Q)[M], const Phys& ph, double (&r)[NPART]) {
   if (SYS == SYS_EULER) {
-    const double rho = Q[0];
-    const double mx = Q[1 % M];
-    const double my = M == 4 ? Q[2 % M] : 0.0;
-    const double E = Q[M - 1];
-    const double ir = rcp_nr(rho);
-    const double u = mx * ir, v = my * ir;
-    const double p = ph.gm1 * fma(-0.5 * rho, fma(u, u, v * v), E);
-    const double c2 = ph.gamma * p * ir;
+    double u, v, p, c2;
+    euler_cell_speed(Q[0], Q[1 % M], M == 4 ? Q[2 % M] : 0.0, Q[M - 1], ph, u, v, p, c2);
     // A NaN or infinite component makes p NaN, -inf or +inf (then c2 = +inf),
     // so these tests also reject every non-finite state; past them all
     // speeds are numbers and fmax needs no NaN care.
-    const bool ok = rho > 0.0 && p > 0.0 && c2 > 0.0 && c2 < __builtin_huge_val();
+    const bool ok = Q[0] > 0.0 && p > 0.0 && c2 > 0.0 && c2 < __builtin_huge_val();
     if (!ok) { r[0] = __builtin_huge_val(); return; }
-    const double c = sqrt_nr(c2);
+    const double c = __builtin_sqrt(c2);
     r[0] = fmax(r[0], fabs(u - c));
     r[1] = fmax(r[1], fabs(u));
     r[2] = fmax(r[2], fabs(u + c));

@@ -228,7 +228,7 @@ static void launch_y_sys(za_ctx* c, int mode, const SweepArgs& a) {
   }
 }
 
-static void launch_x(za_ctx* c, int mode, const SweepArgs& a) {
+void launch_x(za_ctx* c, int mode, const SweepArgs& a) {
   timed_begin(c, 0);
   if (order_of(c->prob) != 3) {
     launch_x_order(c, mode, a);
@@ -246,7 +246,7 @@ static void launch_x(za_ctx* c, int mode, const SweepArgs& a) {
   timed_end(c, 0);
 }
 
-static void launch_y(za_ctx* c, int mode, const SweepArgs& a) {
+void launch_y(za_ctx* c, int mode, const SweepArgs& a) {
   timed_begin(c, 1);
   if (order_of(c->prob) != 3) {
     launch_y_order(c, mode, a);
@@ -268,7 +268,7 @@ static void launch_final(za_ctx* c, int kind, int nblk) {
 }
 
 // Stand-alone wave-speed reduction of q followed by the final reduction.
-static void launch_wave(za_ctx* c, const double* q, int kind, int check_active) {
+void launch_wave(za_ctx* c, const double* q, int kind, int check_active) {
   timed_begin(c, 2);
   const size_t ncell = (size_t)c->prob.nx * c->prob.ny;
   const int nblk = c->red_blocks;
@@ -305,7 +305,7 @@ __global__ void k_ctl_arm(DevCtl* ctl, double dt_fixed, double t_final, long lon
   ctl->active = ctl->bad ? 0 : 1;
 }
 
-static SweepArgs base_args(za_ctx* c) {
+SweepArgs base_args(za_ctx* c) {
   SweepArgs a;
   std::memset(&a, 0, sizeof(a));
   a.ctl = c->ctl;
@@ -489,24 +489,18 @@ static DevCtl fresh_ctl() {
   return v;
 }
 
-// ---------------------------------------------------------------------------
-// C ABI
-// ---------------------------------------------------------------------------
-extern "C" {
+void launch_ctl_reset(za_ctx* c) {
+  hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, c->stream, c->ctl, fresh_ctl());
+}
 
-za_status za_ctx_create(const za_problem* p, void* stream, za_ctx** out) {
-  if (!out) return ZA_ERR_ARG;
-  *out = nullptr;
-  std::string why;
-  za_status st = za_validate(p, &why);
-  if (st != ZA_OK) return st;
-  za_ctx* c = new za_ctx();
+// Everything a context derives from its problem without allocating: the
+// geometry and physics constants, launch shapes and reduction sizes.
+void init_shape(za_ctx* c, const za_problem* p, hipStream_t stream) {
   c->prob = *p;
   c->m = ncomp_of(*p);
-  c->stream = (hipStream_t)stream;
-  hipGetDevice(&c->device);
+  c->stream = stream;
+  (void)hipGetDevice(&c->device);
   const size_t ncell = (size_t)p->nx * p->ny;
-  const size_t st_bytes = (size_t)c->m * ncell * sizeof(double);
   c->geom.nx = p->nx;
   c->geom.ny = p->ny;
   c->geom.bc_x = p->bc_x;
@@ -535,6 +529,22 @@ za_status za_ctx_create(const za_problem* p, void* stream, za_ctx** out) {
     c->stage_blocks = (int)((nseg * p->ny + 3) / 4);
   }
   c->part_blocks = std::max(RED_BLOCKS_MAX, c->stage_blocks);
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+za_status za_ctx_create(const za_problem* p, void* stream, za_ctx** out) {
+  if (!out) return ZA_ERR_ARG;
+  *out = nullptr;
+  std::string why;
+  za_status st = za_validate(p, &why);
+  if (st != ZA_OK) return st;
+  za_ctx* c = new za_ctx();
+  init_shape(c, p, (hipStream_t)stream);
+  const size_t st_bytes = (size_t)c->m * p->nx * p->ny * sizeof(double);
   hipError_t e;
   void* ptr = nullptr;
   if ((e = hipMalloc(&ptr, st_bytes)) != hipSuccess) { delete c; return ZA_ERR_NOMEM; }

@@ -89,3 +89,32 @@ def test_problem_struct_layout_matches_header(tmp_path):
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert got[0] == ctypes.sizeof(za.ZaProblem)
     assert got[1:] == [getattr(za.ZaProblem, f).offset for f in fields]
+
+
+CITATION = re.compile(r"\beq:\w+|\bSection \d|\btab:\w+|\bAppendix\b|[Nn]ot from the paper")
+
+
+def test_every_declared_call_cites_its_passage():
+    """Each entry point's comment names the passage of the paper that
+    defines what it computes, or says that it is not from the paper.  A
+    comment covers the declarations that follow it directly."""
+    lines = open(os.path.join(ROOT, "include", "za.h")).read().splitlines()
+    comment, in_comment, uncited, seen = "", False, [], set()
+    for ln in lines:
+        s = ln.strip()
+        if in_comment or s.startswith("/*"):
+            if not in_comment:
+                comment = ""
+            comment += " " + s
+            in_comment = "*/" not in s
+            continue
+        if s.startswith("}") or s.startswith("typedef"):
+            comment = ""
+            continue
+        m = re.match(r"^(?:const\s+)?[A-Za-z_][A-Za-z_0-9]*\s*\**\s+\**\s*(za_[a-z_0-9]+)\s*\(", s)
+        if m:
+            seen.add(m.group(1))
+            if not CITATION.search(comment):
+                uncited.append(m.group(1))
+    assert seen == set(declared_functions())
+    assert not uncited, uncited

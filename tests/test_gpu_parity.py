@@ -162,6 +162,40 @@ def test_fluxes_weight_variants(dev, variant):
     assert_close(fy, ry, 1e-12, variant)
 
 
+@pytest.mark.parametrize("variant", ["z_eps1e-6", "js_eps1e-6", "ai_mu0_1e-3", "fp32_eps1e-6"])
+@pytest.mark.parametrize("dim", [1, 2])
+def test_fluxes_euler_nondefault_eps(dev, variant, dim):
+    """Euler fluxes with an epsilon (and mu_0) large enough to matter
+    (eq:weight_nonlinear, eq:aimu): a small smooth ripple on Riemann data
+    makes the indicators comparable to epsilon.  The kernels carry the two
+    acoustic characteristic fields scaled by 2c, so they must scale epsilon
+    by 4c^2 (and mu_0 by 2c) to reconstruct what the oracle reconstructs."""
+    kw = {"z_eps1e-6": dict(eps=1e-6), "js_eps1e-6": dict(eps=1e-6, weight_L=0.0, weight_q=1.0, p=2.0),
+          "ai_mu0_1e-3": dict(affine_invariant=1, mu0=1e-3, eps=1e-6), "fp32_eps1e-6": dict(eps=1e-6)}[variant]
+    if dim == 1:
+        P, q0 = W.riemann_1d(4, 300)
+        x = W.centres(300, 0.0, 1.0)
+        q0 = q0.copy()
+        q0[0] *= 1.0 + 1e-2 * np.sin(6 * np.pi * x)
+    else:
+        P, q0 = W.quadrants_2d(9, 70, 66)
+        x = W.centres(70, 0.0, 1.0)[None, :]
+        y = W.centres(66, 0.0, 1.0)[:, None]
+        q0 = q0.copy()
+        q0[0] *= 1.0 + 1e-2 * np.sin(2 * np.pi * (3 * x + 2 * y))
+    P = P.with_(**kw)
+    rel = 1e-12
+    if variant.startswith("fp32"):
+        P = P.fp32().with_(eps=1e-6)
+        rel = 3e-5
+    fx, fy = gpu_fluxes(P, q0, dev)
+    rx, ry, st = orc.fluxes(P, q0)
+    assert st == 0
+    assert_close(fx, rx, rel, f"{variant} fx")
+    if dim == 2:
+        assert_close(fy, ry, rel, f"{variant} fy")
+
+
 # ---------------------------------------------------------------------------
 # right-hand side, steps, solves
 # ---------------------------------------------------------------------------
@@ -209,8 +243,32 @@ def test_step_cfl_dt_and_state(dev):
     with Ctx(P) as ctx:
         dt = ctx.step(q, 0.0, sync=True)
     ref, dt_ref, st = orc.step(P, q0, 0.0)
-    assert abs(dt - dt_ref) <= 1e-15 * dt_ref  # wave speeds via a Newton reciprocal: a few ulp
+    # the wave speeds are maxima of correctly rounded per-cell values and the
+    # CFL rule one more correctly rounded expression: bit for bit
+    assert dt == dt_ref, (dt, dt_ref)
     assert_close(q.cpu().numpy(), ref, 1e-10, "step")
+
+
+@pytest.mark.parametrize("case", ["1d", "2d", "2d_full", "config3"])
+def test_cfl_dt_bitwise(dev, case):
+    """The CFL step of eq:LF's wave speeds equals the oracle's bit for bit:
+    1D and 2D Riemann data, the 2048^2 workload, and the 2D Riemann
+    configuration 3 at 400^2 (CFL 0.45), on the first and a later step."""
+    if case == "1d":
+        P, q0 = W.riemann_1d(3, 4096)
+    elif case == "2d":
+        P, q0 = W.quadrants_2d(12, 130, 67)
+    elif case == "2d_full":
+        P, q0 = W.quadrants_2d(0, 2048)
+    else:
+        P, q0, _ = W.riemann_config3(400)
+    q = torch.from_numpy(q0).to(dev)
+    with Ctx(P) as ctx:
+        dt1 = ctx.step(q, 0.0, sync=True)
+        q1 = q.cpu().numpy()
+        dt2 = ctx.step(q, 0.0, sync=True)
+    assert dt1 == orc.cfl_dt(P, q0)
+    assert dt2 == orc.cfl_dt(P, q1)
 
 
 def test_solve_advection_c0(dev):
