@@ -180,6 +180,23 @@ za_status za_step(za_ctx* ctx, double* q, double dt, double* dt_used);
  * info (host, may be NULL) receives the step statistics.  Synchronises. */
 za_status za_solve(za_ctx* ctx, double* q, double t_final, int64_t max_steps, za_solve_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): za_rhs
+ * without a context.  problem: as for za_ctx_create; q, rhs: device,
+ * m*nx*ny doubles each, must not overlap; hip_stream: the hipStream_t to
+ * enqueue on (NULL = the default stream).  Computes exactly what za_rhs
+ * computes, with the same kernels.  Allocates nothing: the wave-speed
+ * partials and the control block live in one static device array of 48.25
+ * KiB per GPU (held until the process ends), which covers every grid the
+ * library accepts (at most 2^31 cells; the reduction pass strides over the
+ * cells with at most 1024 blocks).  Every call on a GPU shares that GPU's
+ * array and overwrites it: calls that overlap on one GPU (from other streams
+ * or threads) race, and the caller must serialise them.  Asynchronous; a
+ * non-finite state is not reported (za_rhs reports it through a context).
+ * ZA_ERR_ARG for an invalid problem, NULL or overlapping buffers;
+ * ZA_ERR_DEVICE if the device array cannot be found or a launch fails. */
+za_status za_rhs_noalloc(const za_problem* problem, const double* q, double* rhs, void* hip_stream);
+
 /* FP64 totals of each conserved variable, sums[c] = sum over cells of q[c]
  * (the conservative form eq:hyperbolic_1D_scalar_h telescopes, so with
  * periodic boundaries these stay constant up to rounding).  Fixed-order

@@ -21,7 +21,7 @@ ZA_OK, ZA_ERR_ARG, ZA_ERR_NOMEM, ZA_ERR_DEVICE, ZA_ERR_NONFINITE, ZA_ERR_UNSUPPO
 
 EXPORTED = [
     "za_ctx_create", "za_ctx_destroy", "za_ctx_set_stream", "za_state_count", "za_workspace_bytes",
-    "za_rhs", "za_rhs_fluxes", "za_step", "za_solve", "za_conserved_sums", "za_status_str",
+    "za_rhs", "za_rhs_fluxes", "za_rhs_noalloc", "za_step", "za_solve", "za_conserved_sums", "za_status_str",
     "za_ctx_last_error", "za_ctx_set_timing", "za_ctx_kernel_times",
     "za_server_create", "za_server_submit", "za_server_poll", "za_server_drain", "za_server_destroy",
 ]
@@ -101,6 +101,7 @@ def lib() -> C.CDLL:
     L.za_workspace_bytes.restype = C.c_size_t
     L.za_rhs.argtypes = [vp, vp, vp]
     L.za_rhs_fluxes.argtypes = [vp, vp, vp, vp]
+    L.za_rhs_noalloc.argtypes = [PP, vp, vp, vp]
     L.za_step.argtypes = [vp, vp, C.c_double, dp]
     L.za_solve.argtypes = [vp, vp, C.c_double, C.c_int64, C.POINTER(ZaSolveInfo)]
     L.za_conserved_sums.argtypes = [vp, vp, dp]
@@ -142,6 +143,25 @@ def _check_state(P: Problem, t, name="q"):
     if t.dtype != torch.float64 or not t.is_contiguous():
         raise TypeError(f"{name} must be contiguous float64")
     return t
+
+
+def rhs_noalloc(P: Problem, q, out=None, stream=None):
+    """za_rhs_noalloc: L(q) without a context and without any device
+    allocation by the library (the output tensor, if not given, is
+    allocated here by PyTorch).  Asynchronous on `stream` (default: the
+    current stream)."""
+    import torch
+    _check_state(P, q, "q")
+    out = torch.empty_like(q) if out is None else out
+    _check_state(P, out, "rhs")
+    if tuple(q.shape) != tuple(P.shape) or tuple(out.shape) != tuple(P.shape):
+        raise ValueError(f"q and rhs must have shape {tuple(P.shape)}")
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    z = ZaProblem.from_problem(P)
+    st = lib().za_rhs_noalloc(C.byref(z), C.c_void_p(q.data_ptr()), C.c_void_p(out.data_ptr()), C.c_void_p(s))
+    if st != ZA_OK:
+        raise ZaError(st, status_str(st))
+    return out
 
 
 class Context:
