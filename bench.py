@@ -99,32 +99,81 @@ def measured_traffic(kernel):
         return None
 
 
-def run_gpu(P, q0_np, steps, warmup, torch, Context):
+def run_gpu(P, q0_np, steps, warmup, torch, Context, settle_s=0.5, timing_pass=True):
+    """Time `steps` RK3 steps of the product path (za_solve with its captured
+    step graphs, no per-launch events) from q0 resident in HBM.
+
+    Warm-up: `warmup` steps, then calls of the timed length until the GPU
+    has run for at least settle_s seconds (its clocks ramp up over the first
+    tens of milliseconds of load, when a sweep launch takes ~25 % longer),
+    which also captures the step graph before the timed call.
+    Per-kernel times come from a second run of the same steps with one HIP
+    event pair around every launch on the library's stream (which runs the
+    steps as direct launches)."""
     dev = torch.device("cuda:0")
     q0 = torch.from_numpy(q0_np).to(dev)
     q = q0.clone()
     ctx = Context(P)
+    n_warm = 0
+    t_w = time.perf_counter()
     if warmup > 0:
         ctx.solve(q, 0.0, warmup)
-    q.copy_(q0)
+        n_warm += warmup
     torch.cuda.synchronize()
-    ctx.set_timing(True)
+    # calls of the timed length: the first captures the step graph of this
+    # state buffer (a one-time cost that must not land in the timed call)
+    while n_warm < warmup + steps or time.perf_counter() - t_w < settle_s:
+        ctx.solve(q, 0.0, steps)
+        n_warm += steps
+        torch.cuda.synchronize()
+    warm_s = time.perf_counter() - t_w
+    q.copy_(q0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     info = ctx.solve(q, 0.0, steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    avg_ms, counts = ctx.kernel_times()
-    ctx.set_timing(False)
+    avg_ms, counts = [0.0, 0.0, 0.0], [0, 0, 0]
+    if timing_pass:
+        q2 = q0.clone()
+        ctx.set_timing(True)
+        ctx.solve(q2, 0.0, steps)
+        avg_ms, counts = ctx.kernel_times()
+        ctx.set_timing(False)
+        del q2
     ctx.close()
-    return q, t1 - t0, info, avg_ms, counts
+    return q, t1 - t0, info, avg_ms, counts, {"warmup_steps_run": n_warm, "warmup_s": warm_s}
+
+
+def cpu_info():
+    """Host CPU: model name, logical CPUs of the machine (nproc) and of this
+    process's affinity mask, and the thread-count environment."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": aff,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
 
 
 def cpu_baseline(P, q0_np, seconds):
-    """The oracle (as it stands) on the host cores: repeated full 2048^2
-    right-hand sides until `seconds` have elapsed (at least one)."""
+    """The oracle (as it stands) on the host cores: repeated full right-hand
+    sides of the workload until `seconds` have elapsed (at least one), with
+    OpenMP over rows on every CPU this process may use (OMP_NUM_THREADS if
+    set, which is the host's CPU share on a shared GPU machine), and one more on
+    a single thread."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    hw = cpu_info()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or hw["affinity_cpus"] or os.cpu_count() or 1
     oracle.set_threads(threads)
     used = oracle.get_threads()
     n = 0
@@ -139,7 +188,8 @@ def cpu_baseline(P, q0_np, seconds):
     out = {"value": irs, "unit": "IR/s", "cores": used, "kind": "oracle",
            "sample": f"{n} full right-hand side(s) of the 2D Euler {P.nx}x{P.ny} workload "
                      f"(one RK3 stage each, {ir_per_rhs(P.nx, P.ny)} IR) in {dt:.1f} s, FP64, "
-                     f"OpenMP over rows"}
+                     f"OpenMP over rows on {used} threads",
+           "host": hw}
     # the same oracle on one thread (one right-hand side), for reference
     oracle.set_threads(1)
     t0 = time.perf_counter()
@@ -172,7 +222,8 @@ def run_serving(lam, n_requests, budget, slots, seed=None, max_1d=65536, max_2d=
             ids[i] = sv.submit(r.problem, r.q0, r.steps)
         sv.drain()
         t1 = time.perf_counter()
-        lat, irs, fl, statuses, waits = [], 0, 0.0, [], []
+        lat, irs, statuses, waits = [], 0, [], []
+        fl = {0: 0.0, 1: 0.0}   # algorithmic FLOPs of FP64 (0) and FP32-reconstruction (1) requests
         first_arr = None
         last_fin = 0
         for r, rid in zip(reqs, ids):
@@ -185,7 +236,7 @@ def run_serving(lam, n_requests, budget, slots, seed=None, max_1d=65536, max_2d=
             irs += stats["interfaces"]
             m = r.problem.m
             per_ir = FLOPS_2D["x"]["interface"] if m == 4 else FLOPS_1D_IR
-            fl += stats["interfaces"] * per_ir
+            fl[int(r.problem.precision)] += stats["interfaces"] * per_ir
             first_arr = arr if first_arr is None else min(first_arr, arr)
             last_fin = max(last_fin, stats["finish_ns"])
     span = (last_fin - first_arr) * 1e-9
@@ -194,7 +245,13 @@ def run_serving(lam, n_requests, budget, slots, seed=None, max_1d=65536, max_2d=
             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
             "mean_admission_wait_s": float(np.mean(waits)),
             "throughput_req_s": n_requests / span, "throughput_IR_s": irs / span,
-            "roofline_frac": fl / span / (PEAK_FP64_TFLOPS * 1e12), "makespan_s": span,
+            "flop_rate_fp64_requests_TFLOP_s": fl[0] / span / 1e12,
+            "flop_rate_fp32_requests_TFLOP_s": fl[1] / span / 1e12,
+            "roofline_frac_fp64": fl[0] / span / (PEAK_FP64_TFLOPS * 1e12),
+            "roofline_frac_fp32": fl[1] / span / (PEAK_FP32_TFLOPS * 1e12),
+            # share of the vector ALU's issue capacity: non-packed FP32 issues at the FP64 rate
+            "roofline_frac_valu_issue": (fl[0] + fl[1]) / span / (PEAK_FP64_TFLOPS * 1e12),
+            "makespan_s": span,
             "wall_s": t1 - t0}
 
 
@@ -343,7 +400,7 @@ def study_orders(torch, Context, n=2048, steps=20):
     ir_step = 3 * ir_per_rhs(n, n)
     for r in (2, 3, 4, 5):
         Pr = P.with_(order=r)
-        _, wall, info, avg_ms, counts = run_gpu(Pr, q0, steps, 2, torch, Context)
+        _, wall, info, avg_ms, counts, _ = run_gpu(Pr, q0, steps, 2, torch, Context)
         fl = {d: ((n + 1) * n if d == "x" else n * (n + 1)) * FLOPS_2D_ORDER_IR[r] for d in ("x", "y")}
         out["runs"].append({
             "r": r, "order": 2 * r, "steps": steps, "IR_s": ir_step * steps / wall,
@@ -421,7 +478,7 @@ def study_scalar(torch, Context):
     rows = []
     for name, system in (("advection_2d", ADVECTION), ("buckley_2d", BUCKLEY)):
         P = Problem(dim=2, system=system, nx=n, ny=n, bc_x=PERIODIC, bc_y=PERIODIC, adv_speed=(1.0, 0.5))
-        _, wall, info, avg_ms, counts = run_gpu(P, np.ascontiguousarray(base.reshape(1, n, n)), 20, 2, torch,
+        _, wall, info, avg_ms, counts, _ = run_gpu(P, np.ascontiguousarray(base.reshape(1, n, n)), 20, 2, torch,
                                                 Context)
         rows.append({"workload": f"{name} {n}x{n} FP64", "IR_s": 3 * ir_per_rhs(n, n) * 20 / wall,
                      "ms_per_step": wall / 20 * 1e3, "x_ms": avg_ms[0], "y_ms": avg_ms[1]})
@@ -442,7 +499,7 @@ def study_pp(torch, Context, n=2048, steps=20):
     P, q0 = W.quadrants_2d(0, n)
     ir_step = 3 * ir_per_rhs(n, n)
     for pp in (0, 1):
-        _, wall, info, avg_ms, counts = run_gpu(P.with_(pp_limiter=pp, cfl=0.45), q0, steps, 2, torch, Context)
+        _, wall, info, avg_ms, counts, _ = run_gpu(P.with_(pp_limiter=pp, cfl=0.45), q0, steps, 2, torch, Context)
         out["runs"].append({"workload": f"quadrants {n}x{n} CFL 0.45", "pp_limiter": pp, "IR_s": ir_step * steps / wall,
                             "ms_per_step": wall / steps * 1e3, "x_ms": avg_ms[0], "y_ms": avg_ms[1]})
     m = 1024
@@ -500,9 +557,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-rates", type=str, default="50,200",
-                    help="Poisson rates (req/s) of the serving leg; the full sweep is 10,25,50,100,200")
-    ap.add_argument("--serving-requests", type=int, default=128)
+    ap.add_argument("--serving-rates", type=str, default="10,25,50,100,200",
+                    help="Poisson rates (req/s) of the serving leg")
+    ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-budget-gb", type=float, default=4.0)
     ap.add_argument("--study", choices=["c0", "c1", "c3", "orders", "scalar", "pp", "adr", "serving"], default=None,
                     help="run one workload study instead of the benchmark line")
@@ -546,10 +603,14 @@ def main():
     nx, ny = P.nx, P.ny
     ir_step = 3 * ir_per_rhs(nx, ny)
 
-    q64, wall, info, avg_ms, counts = run_gpu(P, q0, args.steps, args.warmup, torch, Context)
+    def log(msg):
+        print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+    q64, wall, info, avg_ms, counts, warm = run_gpu(P, q0, args.steps, args.warmup, torch, Context)
     assert info["steps"] == args.steps, info
     value = ir_step * args.steps / wall
     ms_step = wall / args.steps * 1e3
+    log(f"FP64 {value:.4g} IR/s, {ms_step:.4f} ms/step")
 
     names = ["x-sweep", "y-sweep", "wave-speed"]
     dom = 0 if avg_ms[0] >= avg_ms[1] else 1
@@ -561,6 +622,8 @@ def main():
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(kname),
                 "kernel": f"{kname} (2D Euler FP64)",
                 "avg_launch_ms": avg_ms[dom], "launches": counts[dom],
+                "timing": "HIP events around every launch on the library's stream, in a second run of the "
+                          "same steps after the timed one",
                 "algorithmic_flop_per_launch": fl,
                 "algorithmic_bytes_per_launch": sweep_bytes(nx, ny, d)}
     kernels = {names[k]: {"avg_ms": avg_ms[k], "launches": counts[k]} for k in range(3)}
@@ -584,6 +647,8 @@ def main():
                                f"WENO-ZA6 characteristic-wise, SSP-RK3 CFL 0.5, FP64",
                    "nx": nx, "ny": ny, "seed": args.seed, "ir_per_step": ir_step,
                    "t_final": info["t"]},
+        "timed": "za_solve of the steps (captured step graphs, no per-launch events); state resident in HBM",
+        "warmup_detail": warm,
         "roofline": roofline,
         "kernels": kernels,
         # scalar WENO reconstructions: 2 splits x 4 characteristic fields per IR
@@ -591,33 +656,90 @@ def main():
     }
 
     if not args.no_fp32:
-        P32 = P.fp32()
-        q32, wall32, info32, avg32, cnt32 = run_gpu(P32, q0, args.steps, args.warmup, torch, Context)
-        r64 = q64[0].double()
-        r32 = q32[0].double()
-        e = (r32 - r64).abs()
-        out["fp32"] = {"value": ir_step * args.steps / wall32, "unit": "IR/s",
-                       "ms_per_step": wall32 / args.steps * 1e3,
-                       "density_err_vs_fp64": {"l1": float(e.mean()), "linf": float(e.max())},
-                       "avg_launch_ms": {names[k]: avg32[k] for k in range(3)},
-                       "speedup_vs_fp64": wall / wall32}
+        out["fp32"] = fp32_leg(P, q0, q64, args, torch, Context, log)
 
     if not args.no_serving:
         rates = [float(x) for x in args.serving_rates.split(",") if x]
-        runs = [run_serving(lam, args.serving_requests, int(args.serving_budget_gb * (1 << 30)), 64)
-                for lam in rates]
-        out["serving"] = {"workload": "Poisson stream: half 1D Euler N log-uniform [512, 65536], half 2D "
-                                      "Euler n x n log-uniform [128, 1024]; Riemann or smooth data; 50-500 "
-                                      "RK3 steps; FP64 or FP32 reconstruction (seed = rate)",
+        runs = []
+        for lam in rates:
+            runs.append(run_serving(lam, args.serving_requests, int(args.serving_budget_gb * (1 << 30)), 64))
+            log(f"serving {lam:g} req/s: p50 {runs[-1]['p50_latency_s']:.3f} s, p99 {runs[-1]['p99_latency_s']:.3f} s, "
+                f"{runs[-1]['throughput_IR_s']:.3g} IR/s")
+        out["serving"] = {"workload": f"Poisson stream of {args.serving_requests} requests per rate: half 1D Euler N "
+                                      "log-uniform [512, 65536], half 2D Euler n x n log-uniform [128, 1024]; "
+                                      "Riemann or smooth data; 50-500 RK3 steps; FP64 or FP32 reconstruction "
+                                      "(seed = rate)",
                           "hbm_budget_gb": args.serving_budget_gb, "max_slots": 64, "runs": runs}
-        out["p50_latency_s"] = runs[-1]["p50_latency_s"]
-        out["p99_latency_s"] = runs[-1]["p99_latency_s"]
+        top = max(runs, key=lambda r: r["rate_req_s"])
+        out["p50_latency_s"] = top["p50_latency_s"]
+        out["p99_latency_s"] = top["p99_latency_s"]
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(P, q0, args.cpu_seconds)
         cb["gpu_over_cpu"] = value / cb["value"]
         out["cpu_baseline"] = cb
+        log(f"cpu baseline {cb['value']:.3g} IR/s on {cb['cores']} threads")
     print(json.dumps(out), flush=True)
+
+
+def fp32_leg(P, q0, q64, args, torch, Context, log, oracle_steps=10):
+    """FP32 reconstruction on the same workload: throughput, the slower sweep
+    against the FP32 vector peak, and the density error of the FP32 result
+    (i) against the FP64 GPU run after the timed steps and (ii) against the
+    FP64 oracle after `oracle_steps` steps, next to the FP64 GPU run's own
+    distance to the oracle there (which ties (i) to the oracle)."""
+    import numpy as np
+
+    import oracle
+    nx, ny = P.nx, P.ny
+    ir_step = 3 * ir_per_rhs(nx, ny)
+    P32 = P.fp32()
+    q32, wall32, info32, avg32, cnt32, warm32 = run_gpu(P32, q0, args.steps, args.warmup, torch, Context)
+    names = ["x-sweep", "y-sweep", "wave-speed"]
+    r64 = q64[0].double()
+    e = (q32[0].double() - r64).abs()
+    res = {"value": ir_step * args.steps / wall32, "unit": "IR/s",
+           "ms_per_step": wall32 / args.steps * 1e3,
+           "density_err_vs_gpu_fp64": {"steps": args.steps, "l1": float(e.mean()), "linf": float(e.max())},
+           "avg_launch_ms": {names[k]: avg32[k] for k in range(3)},
+           "warmup_detail": warm32}
+    log(f"FP32 reconstruction {res['value']:.4g} IR/s")
+    dom = 0 if avg32[0] >= avg32[1] else 1
+    d = "x" if dom == 0 else "y"
+    fl = sweep_flops(nx, ny, d)
+    ach = fl / (avg32[dom] * 1e-3) / 1e12
+    res["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                       "frac": ach / PEAK_FP32_TFLOPS, "kernel": f"k_sweep_{d} (2D Euler FP32 reconstruction)",
+                       "avg_launch_ms": avg32[dom],
+                       "note": "FP32 vector peak with packed FP32 issue; the library is built without packed "
+                               "FP32 instructions, whose non-packed issue rate equals the FP64 rate (78.6)",
+                       "frac_of_unpacked_issue_rate": ach / PEAK_FP64_TFLOPS,
+                       "algorithmic_flop_per_launch": fl,
+                       "algorithmic_bytes_per_launch": sweep_bytes(nx, ny, d),
+                       "hbm_GB_s_algorithmic": sweep_bytes(nx, ny, d) / (avg32[dom] * 1e-3) / 1e9}
+    # against the FP64 oracle after a few steps
+    n = min(oracle_steps, args.steps)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
+    oracle.set_threads(threads)
+    t0 = time.perf_counter()
+    ref, steps, t, st = oracle.solve(P, q0, 0.0, n)
+    t_orc = time.perf_counter() - t0
+    got = {}
+    for name, PP in (("fp64", P), ("fp32", P32)):
+        q = torch.from_numpy(q0).to("cuda")
+        with Context(PP) as ctx:
+            ctx.solve(q, 0.0, n)
+        got[name] = q.cpu().numpy()
+        del q
+    e32 = np.abs(got["fp32"][0] - ref[0])
+    e64 = np.abs(got["fp64"][0] - ref[0])
+    res["density_err_vs_fp64_oracle"] = {
+        "steps": n, "l1": float(e32.mean()), "linf": float(e32.max()),
+        "gpu_fp64_vs_oracle": {"l1": float(e64.mean()), "linf": float(e64.max())},
+        "oracle_s": t_orc, "oracle_threads": oracle.get_threads()}
+    log(f"FP32 density vs oracle after {n} steps: L1 {e32.mean():.3g}, Linf {e32.max():.3g} "
+        f"(FP64 GPU: Linf {e64.max():.3g})")
+    return res
 
 
 if __name__ == "__main__":

@@ -529,6 +529,9 @@ void init_shape(za_ctx* c, const za_problem* p, hipStream_t stream) {
     c->stage_blocks = (int)((nseg * p->ny + 3) / 4);
   }
   c->part_blocks = std::max(RED_BLOCKS_MAX, c->stage_blocks);
+  // ZA_STEP_GRAPHS=0 runs the steps of za_solve as direct launches instead
+  // of replaying captured step graphs (results are identical)
+  if (const char* e = std::getenv("ZA_STEP_GRAPHS")) c->graphs_ok = std::atoi(e) != 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -225,12 +225,23 @@ struct Req {
   int64_t launched = 0;    // RK3 steps enqueued since admission
 };
 
-// RK3 steps a class runs between two synchronisations of the scheduler: as
-// many as the active request closest to its step count still needs (so no
-// request finishes later than with one step per pass and no launched step
-// is idle for all of them), at most SERVE_MAX_BURST (new arrivals wait at
-// most that many steps for admission).
+// One burst of RK3 steps of a class in flight: the requests it advanced, the
+// host buffers it used (table upload, control-block mirror) and the event
+// recorded after its mirror copy.
+struct Burst {
+  int buf = 0;
+  hipEvent_t ev = nullptr;
+  std::vector<Req*> members;
+};
+
+// RK3 steps of a class per burst: SERVE_MAX_BURST, or fewer when every
+// active request needs fewer.  A request that reaches its step count stops
+// on the device (its control block turns inactive and its blocks exit at
+// once), so it ends mid-burst and never waits for the others.  Each class
+// keeps SERVE_DEPTH bursts queued on its stream, so the GPU works on the
+// next burst while the host retires and admits requests.
 constexpr int SERVE_MAX_BURST = 8;
+constexpr int SERVE_DEPTH = 2;
 
 static int class_of(const za_problem& p) { return (p.dim == 2 ? 2 : 0) + (p.precision == ZA_FP32_RECON ? 1 : 0); }
 static int ncomp(const za_problem& p) { return p.dim == 1 ? 3 : 4; }
@@ -245,12 +256,14 @@ struct GraphKey {
 struct Class {
   hipStream_t stream = nullptr;
   BatchTable* dtab = nullptr;
-  BatchTable* htab = nullptr;     // pinned mirror
-  DevCtl* dctl = nullptr;         // MAX_SLOTS control blocks
-  DevCtl* hctl = nullptr;         // pinned mirror
+  BatchTable* htab[SERVE_DEPTH] = {};   // pinned: the table each queued burst uploaded
+  DevCtl* dctl = nullptr;               // MAX_SLOTS control blocks
+  DevCtl* hctl[SERVE_DEPTH] = {};       // pinned: control blocks after each queued burst
+  hipEvent_t ev[SERVE_DEPTH] = {};
+  std::deque<Burst> inflight;           // oldest first
   std::vector<Req*> active;
   std::vector<int> free_slots;
-  bool dirty = false;
+  bool dirty = true;                    // the device table lags behind `active`
   std::map<GraphKey, hipGraphExec_t> graphs;
 };
 
@@ -267,6 +280,7 @@ struct za_server {
   Class cls[NCLASS];
   std::deque<Req*> waiting;
   std::map<za_req_id, std::unique_ptr<Req>> reqs;
+  hipStream_t xfer = nullptr;     // uploads and result downloads, beside the compute streams
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::thread th;
@@ -274,6 +288,10 @@ struct za_server {
   za_req_id next_id = 1;
   int64_t in_flight = 0;   // submitted and not finished
   std::string err;
+  // host-side fault injection for tests of the failure path
+  // (ZA_SRV_FAIL_BURST=k: the k-th burst launch reports a launch error)
+  int64_t fail_burst = 0, bursts = 0;
+  bool graphs = true;   // replay a captured graph per class step (ZA_SRV_GRAPHS=0: direct launches)
 };
 
 // Chunks per segment of the looped x-sweep, which FP64 requests always use
@@ -315,36 +333,45 @@ static int pow2_cap(int n, int lo) {
   return c;
 }
 
-// Launch one RK3 step of a class (captured into a graph per capacity).
-static hipError_t class_step(za_server* sv, int c) {
-  Class& C = sv->cls[c];
-  const BatchTable& h = *C.htab;
+// Launch one RK3 step of a class (captured into a graph per capacity) for
+// the table h, which the device table holds by the time the step runs.
+static void enqueue_class_step(Class& C, int c, const GraphKey& key) {
   const bool two_d = c >= 2, fp32 = (c & 1) != 0;
+  for (int s = 0; s < 3; ++s) {
+    hipLaunchKernelGGL(kb_final, dim3(key.ncap), dim3(64), 0, C.stream, C.dtab, s == 0 ? FIN_STAGE0 : FIN_STAGEK,
+                       two_d ? 2 : 1);
+    if (two_d) {
+      if (fp32) {
+        hipLaunchKernelGGL((kb_sweep_x<4, float>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
+        hipLaunchKernelGGL((kb_sweep_y<float>), dim3(key.ycap), dim3(256), 0, C.stream, C.dtab, s);
+      } else {
+        hipLaunchKernelGGL((kb_sweep_xl<4>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
+        hipLaunchKernelGGL((kb_sweep_y<double>), dim3(key.ycap), dim3(256), 0, C.stream, C.dtab, s);
+      }
+    } else {
+      if (fp32)
+        hipLaunchKernelGGL((kb_sweep_x<3, float>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
+      else
+        hipLaunchKernelGGL((kb_sweep_xl<3>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
+    }
+  }
+  hipLaunchKernelGGL(kb_step_end, dim3(key.ncap), dim3(64), 0, C.stream, C.dtab);
+}
+
+static hipError_t class_step(za_server* sv, int c, const BatchTable& h) {
+  Class& C = sv->cls[c];
+  const bool two_d = c >= 2;
   GraphKey key{pow2_cap(h.xtot, 64), two_d ? pow2_cap(h.ytot, 64) : 0, pow2_cap(h.n, 8)};
+  if (!sv->graphs) {   // direct launches: exact grids
+    enqueue_class_step(C, c, GraphKey{std::max(h.xtot, 1), two_d ? std::max(h.ytot, 1) : 0, std::max(h.n, 1)});
+    return hipGetLastError();
+  }
   auto it = C.graphs.find(key);
   if (it == C.graphs.end()) {
     hipGraph_t g;
     hipError_t e = hipStreamBeginCapture(C.stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    for (int s = 0; s < 3; ++s) {
-      hipLaunchKernelGGL(kb_final, dim3(key.ncap), dim3(64), 0, C.stream, C.dtab, s == 0 ? FIN_STAGE0 : FIN_STAGEK,
-                         two_d ? 2 : 1);
-      if (two_d) {
-        if (fp32) {
-          hipLaunchKernelGGL((kb_sweep_x<4, float>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
-          hipLaunchKernelGGL((kb_sweep_y<float>), dim3(key.ycap), dim3(256), 0, C.stream, C.dtab, s);
-        } else {
-          hipLaunchKernelGGL((kb_sweep_xl<4>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
-          hipLaunchKernelGGL((kb_sweep_y<double>), dim3(key.ycap), dim3(256), 0, C.stream, C.dtab, s);
-        }
-      } else {
-        if (fp32)
-          hipLaunchKernelGGL((kb_sweep_x<3, float>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
-        else
-          hipLaunchKernelGGL((kb_sweep_xl<3>), dim3(key.xcap), dim3(256), 0, C.stream, C.dtab, s);
-      }
-    }
-    hipLaunchKernelGGL(kb_step_end, dim3(key.ncap), dim3(64), 0, C.stream, C.dtab);
+    enqueue_class_step(C, c, key);
     e = hipStreamEndCapture(C.stream, &g);
     if (e != hipSuccess) return e;
     hipGraphExec_t ex;
@@ -356,8 +383,7 @@ static hipError_t class_step(za_server* sv, int c) {
   return hipGraphLaunch(it->second, C.stream);
 }
 
-static void rebuild_table(Class& C) {
-  BatchTable& h = *C.htab;
+static void rebuild_table(const Class& C, BatchTable& h) {
   h.n = (int)C.active.size();
   int x = 0, y = 0;
   for (int i = 0; i < h.n; ++i) {
@@ -373,11 +399,47 @@ static void rebuild_table(Class& C) {
   h.ytot = y;
 }
 
-// Admit waiting requests that fit (first fit in arrival order).  Called with
-// the lock held; the uploads run on the class streams.
-static void admit(za_server* sv) {
+// Mark r finished with status st (its result, if any, already in r->qout),
+// give back its pool space and control-block slot, and wake waiters.
+// Called with the lock held.
+static void finish_req(za_server* sv, Req* r, int st) {
+  if (r->done) return;
+  Class& C = sv->cls[r->cls];
+  r->status = st;
+  if (r->bytes) sv->pool.release(r->off, r->bytes);
+  r->bytes = 0;
+  if (r->slot >= 0) C.free_slots.push_back(r->slot);
+  r->slot = -1;
+  r->done = true;
+  r->t_fin = now_ns();
+  sv->in_flight--;
+  C.active.erase(std::remove(C.active.begin(), C.active.end(), r), C.active.end());
+  for (Burst& b : C.inflight) b.members.erase(std::remove(b.members.begin(), b.members.end(), r), b.members.end());
+  C.dirty = true;
+  std::vector<double>().swap(r->q0);
+}
+
+// A device failure in class c: drain its stream and end every request it
+// holds with ZA_ERR_DEVICE (lock held).
+static void fail_class(za_server* sv, int c, const char* what) {
+  Class& C = sv->cls[c];
+  sv->err = what;
+  (void)hipStreamSynchronize(C.stream);
+  (void)hipGetLastError();
+  C.inflight.clear();
+  while (!C.active.empty()) finish_req(sv, C.active.back(), ZA_ERR_DEVICE);
+  sv->cv_done.notify_all();
+}
+
+// Admit waiting requests that fit (first fit in arrival order).  Pool space
+// and slots are taken under the lock; the initial states are uploaded with
+// the lock released, on the transfer stream (so an upload waits neither for
+// the queued bursts nor blocks submit and poll), and the control block and
+// the wave speeds of Q^0 are then enqueued on the class stream.
+static void admit(za_server* sv, std::unique_lock<std::mutex>& lk) {
   int total = 0;
   for (int c = 0; c < NCLASS; ++c) total += (int)sv->cls[c].active.size();
+  std::vector<Req*> picked;
   for (auto it = sv->waiting.begin(); it != sv->waiting.end();) {
     Req* r = *it;
     Class& C = sv->cls[r->cls];
@@ -413,8 +475,24 @@ static void admit(za_server* sv) {
     d.ph.pp = 0;   // requests with the limiter are not admitted
     d.eps16 = 16.0 * p.eps; d.eps4 = 4.0 * p.eps; d.mu0x2 = 2.0 * p.mu0;
     d.xblocks = xb; d.ystrips = ys; d.yblocks = yb; d.stage_blocks = sb; d.xl_chunks = xc;
-    // upload, control block, and the wave speeds of Q^0
-    (void)hipMemcpyAsync(d.st, r->q0.data(), r->m * r->ncell * sizeof(double), hipMemcpyHostToDevice, C.stream);
+    picked.push_back(r);
+    ++total;
+    it = sv->waiting.erase(it);
+  }
+  if (picked.empty()) return;
+  lk.unlock();
+  std::vector<int> ok(picked.size(), 1);
+  for (size_t k = 0; k < picked.size(); ++k) {
+    Req* r = picked[k];
+    ok[k] = hipMemcpyAsync(r->desc.st, r->q0.data(), r->m * r->ncell * sizeof(double), hipMemcpyHostToDevice,
+                           sv->xfer) == hipSuccess;
+  }
+  const bool up = hipStreamSynchronize(sv->xfer) == hipSuccess;
+  for (size_t k = 0; k < picked.size(); ++k) {
+    Req* r = picked[k];
+    if (!up || !ok[k]) continue;
+    Class& C = sv->cls[r->cls];
+    const SlotDesc& d = r->desc;
     DevCtl v;
     std::memset(&v, 0, sizeof(v));
     v.t_final = std::numeric_limits<double>::infinity();
@@ -422,83 +500,152 @@ static void admit(za_server* sv) {
     v.bad_step = -1;
     v.active = 1;
     v.max_steps = r->n_steps;
+    // stream order puts this after the queued bursts, which may still see
+    // the slot's previous request (inactive) in their tables
     hipLaunchKernelGGL(k_ctl_set, dim3(1), dim3(64), 0, C.stream, d.ctl, v);
-    if (p.dim == 2)
-      hipLaunchKernelGGL((k_wave_partial<SYS_EULER, 4>), dim3(sb), dim3(256), 0, C.stream, d.st, r->ncell, d.ph,
-                         d.ctl, 0, d.part);
+    if (r->prob.dim == 2)
+      hipLaunchKernelGGL((k_wave_partial<SYS_EULER, 4>), dim3(d.stage_blocks), dim3(256), 0, C.stream, d.st,
+                         r->ncell, d.ph, d.ctl, 0, d.part);
     else
-      hipLaunchKernelGGL((k_wave_partial<SYS_EULER, 3>), dim3(sb), dim3(256), 0, C.stream, d.st, r->ncell, d.ph,
-                         d.ctl, 0, d.part);
-    (void)hipStreamSynchronize(C.stream);   // q0 may be released after this
-    std::vector<double>().swap(r->q0);
+      hipLaunchKernelGGL((k_wave_partial<SYS_EULER, 3>), dim3(d.stage_blocks), dim3(256), 0, C.stream, d.st,
+                         r->ncell, d.ph, d.ctl, 0, d.part);
+    ok[k] = hipGetLastError() == hipSuccess;
+  }
+  lk.lock();
+  for (size_t k = 0; k < picked.size(); ++k) {
+    Req* r = picked[k];
+    Class& C = sv->cls[r->cls];
     r->admitted = true;
     r->t_adm = now_ns();
     C.active.push_back(r);
     C.dirty = true;
-    ++total;
-    it = sv->waiting.erase(it);
+    if (!up || !ok[k]) {
+      sv->err = "request upload failed";
+      finish_req(sv, r, ZA_ERR_DEVICE);
+    } else {
+      std::vector<double>().swap(r->q0);
+    }
+  }
+}
+
+// Queue one burst of RK3 steps of class c (lock held): upload the table if
+// the active set changed, launch the steps, copy the control blocks back
+// and record an event.
+static void launch_burst(za_server* sv, int c) {
+  Class& C = sv->cls[c];
+  int buf = 0;
+  if (!C.inflight.empty()) buf = 1 - C.inflight.back().buf;
+  BatchTable& h = *C.htab[buf];
+  rebuild_table(C, h);
+  if (C.dirty) {
+    if (hipMemcpyAsync(C.dtab, &h, sizeof(BatchTable), hipMemcpyHostToDevice, C.stream) != hipSuccess) {
+      fail_class(sv, c, "table upload failed");
+      return;
+    }
+    C.dirty = false;
+  }
+  int64_t burst = 1;
+  for (const Req* r : C.active) burst = std::max(burst, r->n_steps - r->launched);
+  burst = std::min<int64_t>(burst, SERVE_MAX_BURST);
+  ++sv->bursts;
+  if (sv->fail_burst > 0 && sv->bursts == sv->fail_burst) {
+    fail_class(sv, c, "graph launch failed (injected)");
+    return;
+  }
+  for (int64_t k = 0; k < burst; ++k) {
+    if (class_step(sv, c, h) != hipSuccess) {
+      fail_class(sv, c, "graph launch failed");
+      return;
+    }
+  }
+  for (Req* r : C.active) r->launched += burst;
+  if (hipMemcpyAsync(C.hctl[buf], C.dctl, MAX_SLOTS * sizeof(DevCtl), hipMemcpyDeviceToHost, C.stream) != hipSuccess ||
+      hipEventRecord(C.ev[buf], C.stream) != hipSuccess) {
+    fail_class(sv, c, "control block copy failed");
+    return;
+  }
+  Burst b;
+  b.buf = buf;
+  b.ev = C.ev[buf];
+  b.members = C.active;
+  C.inflight.push_back(std::move(b));
+}
+
+// The requests a completed burst finished (lock held).
+static void collect_finished(za_server* sv, int c, const Burst& b, std::vector<Req*>* out) {
+  const DevCtl* hc = sv->cls[c].hctl[b.buf];
+  for (Req* r : b.members) {
+    const DevCtl& h = hc[r->slot];
+    if (h.active) continue;
+    r->steps = h.steps;
+    const long long irs = r->prob.dim == 2 ? (long long)(r->prob.nx + 1) * r->prob.ny +
+                                                 (long long)r->prob.nx * (r->prob.ny + 1)
+                                           : (long long)(r->prob.nx + 1);
+    r->interfaces = 3 * irs * h.steps;
+    r->status = h.bad ? ZA_ERR_NONFINITE : ZA_OK;
+    out->push_back(r);
   }
 }
 
 static void scheduler(za_server* sv) {
   (void)hipSetDevice(sv->device);
   std::unique_lock<std::mutex> lk(sv->mu);
+  std::vector<Req*> fin;
   while (true) {
-    admit(sv);
+    admit(sv, lk);
     bool any = false;
-    for (int c = 0; c < NCLASS; ++c) any = any || !sv->cls[c].active.empty();
+    for (int c = 0; c < NCLASS; ++c) {
+      Class& C = sv->cls[c];
+      if (!C.active.empty() && (int)C.inflight.size() < SERVE_DEPTH) launch_burst(sv, c);
+      any = any || !C.active.empty() || !C.inflight.empty();
+    }
     if (!any) {
       if (sv->stop) break;
       sv->cv_work.wait(lk, [&] { return sv->stop || !sv->waiting.empty(); });
       continue;
     }
-    // table uploads and a burst of RK3 steps per class (streams overlap)
+    // completed bursts, oldest first per class
+    bool progressed = false;
+    fin.clear();
     for (int c = 0; c < NCLASS; ++c) {
       Class& C = sv->cls[c];
-      if (C.active.empty()) continue;
-      if (C.dirty) {
-        rebuild_table(C);
-        (void)hipMemcpyAsync(C.dtab, C.htab, sizeof(BatchTable), hipMemcpyHostToDevice, C.stream);
-        C.dirty = false;
+      while (!C.inflight.empty()) {
+        const hipError_t q = hipEventQuery(C.inflight.front().ev);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) {
+          fail_class(sv, c, "burst failed");
+          break;
+        }
+        collect_finished(sv, c, C.inflight.front(), &fin);
+        C.inflight.pop_front();
+        progressed = true;
       }
-      int64_t burst = SERVE_MAX_BURST;
-      for (const Req* r : C.active) burst = std::min(burst, r->n_steps - r->launched);
-      burst = std::max<int64_t>(burst, 1);
-      for (int64_t k = 0; k < burst; ++k)
-        if (class_step(sv, c) != hipSuccess) sv->err = "graph launch failed";
-      for (Req* r : C.active) r->launched += burst;
-      (void)hipMemcpyAsync(C.hctl, C.dctl, MAX_SLOTS * sizeof(DevCtl), hipMemcpyDeviceToHost, C.stream);
     }
-    lk.unlock();
-    for (int c = 0; c < NCLASS; ++c)
-      if (!sv->cls[c].active.empty()) (void)hipStreamSynchronize(sv->cls[c].stream);
-    lk.lock();
-    // retire finished requests
-    for (int c = 0; c < NCLASS; ++c) {
-      Class& C = sv->cls[c];
-      for (size_t i = 0; i < C.active.size();) {
-        Req* r = C.active[i];
-        const DevCtl& h = C.hctl[r->slot];
-        if (h.active) { ++i; continue; }
-        r->steps = h.steps;
-        const long long irs = r->prob.dim == 2 ? (long long)(r->prob.nx + 1) * r->prob.ny +
-                                                     (long long)r->prob.nx * (r->prob.ny + 1)
-                                               : (long long)(r->prob.nx + 1);
-        r->interfaces = 3 * irs * h.steps;
-        r->status = h.bad ? ZA_ERR_NONFINITE : ZA_OK;
+    if (!fin.empty()) {
+      // copy the results out with the lock released (the other classes'
+      // bursts keep running); a request leaves the device only afterwards
+      std::sort(fin.begin(), fin.end());
+      fin.erase(std::unique(fin.begin(), fin.end()), fin.end());
+      lk.unlock();
+      std::vector<int> ok(fin.size(), 1);
+      for (size_t k = 0; k < fin.size(); ++k) {
+        Req* r = fin[k];
         r->qout.resize(r->m * r->ncell);
-        (void)hipMemcpy(r->qout.data(), r->desc.st, r->m * r->ncell * sizeof(double), hipMemcpyDeviceToHost);
-        sv->pool.release(r->off, r->bytes);
-        C.free_slots.push_back(r->slot);
-        r->slot = -1;
-        r->done = true;
-        r->t_fin = now_ns();
-        sv->in_flight--;
-        C.active.erase(C.active.begin() + i);
-        C.dirty = true;
+        ok[k] = hipMemcpyAsync(r->qout.data(), r->desc.st, r->m * r->ncell * sizeof(double),
+                               hipMemcpyDeviceToHost, sv->xfer) == hipSuccess;
       }
+      const bool down = hipStreamSynchronize(sv->xfer) == hipSuccess;
+      lk.lock();
+      for (size_t k = 0; k < fin.size(); ++k) {
+        if (!down || !ok[k]) sv->err = "result download failed";
+        finish_req(sv, fin[k], (!down || !ok[k]) ? (int)ZA_ERR_DEVICE : fin[k]->status);
+      }
+      sv->cv_done.notify_all();
     }
-    sv->cv_done.notify_all();
+    if (!progressed) {
+      // nothing finished yet: sleep briefly (a submission wakes us)
+      sv->cv_work.wait_for(lk, std::chrono::microseconds(50));
+    }
   }
 }
 
@@ -511,29 +658,38 @@ za_status za_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t d
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return ZA_ERR_ARG;
   auto sv = std::make_unique<za_server>();
+  // on failure, free whatever was created so far (no scheduler thread yet)
+  auto fail = [&](za_status st) { za_server_destroy(sv.release()); return st; };
   sv->budget = hbm_budget_bytes;
   sv->max_slots = max_slots;
   sv->device = device;
-  if (hipSetDevice(device) != hipSuccess) return ZA_ERR_DEVICE;
+  if (const char* e = std::getenv("ZA_SRV_FAIL_BURST")) sv->fail_burst = std::atoll(e);
+  if (const char* e = std::getenv("ZA_SRV_GRAPHS")) sv->graphs = std::atoi(e) != 0;
+  if (hipSetDevice(device) != hipSuccess) return fail(ZA_ERR_DEVICE);
   void* p = nullptr;
-  if (hipMalloc(&p, hbm_budget_bytes) != hipSuccess) return ZA_ERR_NOMEM;
+  if (hipMalloc(&p, hbm_budget_bytes) != hipSuccess) return fail(ZA_ERR_NOMEM);
   sv->pool_base = (char*)p;
   sv->pool.init(hbm_budget_bytes);
+  // non-blocking streams: nothing here waits on the null stream
+  if (hipStreamCreateWithFlags(&sv->xfer, hipStreamNonBlocking) != hipSuccess) return fail(ZA_ERR_DEVICE);
   for (int c = 0; c < NCLASS; ++c) {
     Class& C = sv->cls[c];
-    if (hipStreamCreate(&C.stream) != hipSuccess) return ZA_ERR_DEVICE;
-    if (hipMalloc(&p, sizeof(BatchTable)) != hipSuccess) return ZA_ERR_NOMEM;
+    if (hipStreamCreateWithFlags(&C.stream, hipStreamNonBlocking) != hipSuccess) return fail(ZA_ERR_DEVICE);
+    if (hipMalloc(&p, sizeof(BatchTable)) != hipSuccess) return fail(ZA_ERR_NOMEM);
     C.dtab = (BatchTable*)p;
-    if (hipHostMalloc(&p, sizeof(BatchTable), hipHostMallocDefault) != hipSuccess) return ZA_ERR_NOMEM;
-    C.htab = (BatchTable*)p;
-    std::memset(C.htab, 0, sizeof(BatchTable));
-    if (hipMalloc(&p, MAX_SLOTS * sizeof(DevCtl)) != hipSuccess) return ZA_ERR_NOMEM;
+    if (hipMalloc(&p, MAX_SLOTS * sizeof(DevCtl)) != hipSuccess) return fail(ZA_ERR_NOMEM);
     C.dctl = (DevCtl*)p;
-    if (hipHostMalloc(&p, MAX_SLOTS * sizeof(DevCtl), hipHostMallocDefault) != hipSuccess) return ZA_ERR_NOMEM;
-    C.hctl = (DevCtl*)p;
-    std::memset(C.hctl, 0, MAX_SLOTS * sizeof(DevCtl));
+    for (int b = 0; b < SERVE_DEPTH; ++b) {
+      if (hipHostMalloc(&p, sizeof(BatchTable), hipHostMallocDefault) != hipSuccess) return fail(ZA_ERR_NOMEM);
+      C.htab[b] = (BatchTable*)p;
+      std::memset(C.htab[b], 0, sizeof(BatchTable));
+      if (hipHostMalloc(&p, MAX_SLOTS * sizeof(DevCtl), hipHostMallocDefault) != hipSuccess) return fail(ZA_ERR_NOMEM);
+      C.hctl[b] = (DevCtl*)p;
+      std::memset(C.hctl[b], 0, MAX_SLOTS * sizeof(DevCtl));
+      if (hipEventCreateWithFlags(&C.ev[b], hipEventDisableTiming) != hipSuccess) return fail(ZA_ERR_DEVICE);
+    }
     for (int s = MAX_SLOTS - 1; s >= 0; --s) C.free_slots.push_back(s);
-    (void)hipMemcpy(C.dtab, C.htab, sizeof(BatchTable), hipMemcpyHostToDevice);
+    if (hipMemcpy(C.dtab, C.htab[0], sizeof(BatchTable), hipMemcpyHostToDevice) != hipSuccess) return fail(ZA_ERR_DEVICE);
   }
   za_server* raw = sv.release();
   raw->th = std::thread(scheduler, raw);
@@ -620,10 +776,17 @@ za_status za_server_destroy(za_server* sv) {
     if (C.stream) (void)hipStreamSynchronize(C.stream);
     for (auto& kv : C.graphs) (void)hipGraphExecDestroy(kv.second);
     if (C.dtab) (void)hipFree(C.dtab);
-    if (C.htab) (void)hipHostFree(C.htab);
     if (C.dctl) (void)hipFree(C.dctl);
-    if (C.hctl) (void)hipHostFree(C.hctl);
+    for (int b = 0; b < SERVE_DEPTH; ++b) {
+      if (C.htab[b]) (void)hipHostFree(C.htab[b]);
+      if (C.hctl[b]) (void)hipHostFree(C.hctl[b]);
+      if (C.ev[b]) (void)hipEventDestroy(C.ev[b]);
+    }
     if (C.stream) (void)hipStreamDestroy(C.stream);
+  }
+  if (sv->xfer) {
+    (void)hipStreamSynchronize(sv->xfer);
+    (void)hipStreamDestroy(sv->xfer);
   }
   if (sv->pool_base) (void)hipFree(sv->pool_base);
   delete sv;

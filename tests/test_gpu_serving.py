@@ -128,3 +128,46 @@ def test_served_chunk_counts_bitwise(dev, monkeypatch):
             assert st == 0 and stats["steps"] == 12, (nc, i, st)
             assert np.array_equal(q, ref[i]), (nc, i)
     monkeypatch.delenv("ZA_SRV_XL_CHUNKS")
+
+
+def test_requests_finish_mid_burst_bitwise(dev):
+    """Requests with very different step counts share bursts of up to eight
+    RK3 steps; each stops on the device at its own count (and later bursts
+    skip it), so every result equals the single context's run of exactly
+    that many steps."""
+    steps = (1, 2, 3, 9, 17, 40)
+    cases = [W.riemann_1d(20 + i, 700 + 50 * i) for i in range(3)] + \
+            [W.quadrants_2d(30 + i, 96 + 8 * i, 80) for i in range(3)]
+    reqs = [(P, q0, n) for (P, q0), n in zip(cases, steps)]
+    res = serve(reqs)
+    for (P, q0, n), (st, q, stats) in zip(reqs, res):
+        assert st == 0 and stats["steps"] == n, (n, st, stats["steps"])
+        assert np.array_equal(q, ctx_solve(P, q0, n, dev)), n
+
+
+def test_injected_launch_failure_ends_requests_without_hang(dev, monkeypatch):
+    """A launch failure (injected on the host: ZA_SRV_FAIL_BURST=1 makes the
+    first burst report a launch error, no kernel is touched) ends every
+    request of the failing class with ZA_ERR_DEVICE and releases it, so
+    drain returns instead of waiting forever; requests admitted afterwards
+    run normally, and a new server is unaffected."""
+    from paper_2603_26272_amd import za
+    monkeypatch.setenv("ZA_SRV_FAIL_BURST", "1")
+    reqs = [(*W.riemann_1d(40 + s, 800), 12) for s in range(4)]
+    statuses = []
+    with za.Server(1 << 30, 16) as sv:
+        monkeypatch.delenv("ZA_SRV_FAIL_BURST")
+        ids = [sv.submit(P, q0, n) for P, q0, n in reqs]
+        with pytest.raises(za.ZaError) as ei:
+            sv.drain()
+        assert ei.value.status == za.ZA_ERR_DEVICE
+        for rid, (P, q0, n) in zip(ids, reqs):
+            done, st, q, stats = sv.poll(rid, P)
+            assert done
+            statuses.append(st)
+            if st == 0:
+                assert np.array_equal(q, ctx_solve(P, q0, n, dev))
+    assert za.ZA_ERR_DEVICE in statuses
+    assert all(s in (0, za.ZA_ERR_DEVICE) for s in statuses)
+    res = serve(reqs[:2])
+    assert all(r[0] == 0 for r in res)
