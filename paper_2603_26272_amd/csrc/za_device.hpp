@@ -63,23 +63,32 @@ __device__ __forceinline__ double div_nr(double a, double x) {
 }
 __device__ __forceinline__ float rcp_nr(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Square root of a positive normal number from the hardware reciprocal square
-// root estimate: one Goldschmidt iteration (s -> sqrt(x), h -> 1/(2 sqrt(x)))
-// followed by two residual corrections s <- s + h (x - s^2), which round
-// correctly for estimates within 1e-7.  Densities and squared sound speeds
-// stay far from the denormal and overflow ranges, so the exponent scaling of
-// the library square root is not needed.
-__device__ __forceinline__ double sqrt_nr(double x) {
+__device__ __forceinline__ float div_nr(float a, float x) { return a * __builtin_amdgcn_rcpf(x); }
+
+// Square root s and half reciprocal square root h = 1/(2 sqrt(x)) of a
+// positive normal number together: the hardware reciprocal-square-root
+// estimate refined by coupled Goldschmidt iterations (e = 1/2 - h s,
+// s <- s + s e, h <- h + h e), each of which squares the relative error;
+// two suffice in FP64 (to about an ulp), one in FP32.
+__device__ __forceinline__ void sqrt_rsq(double x, double& s, double& h) {
   const double r = __builtin_amdgcn_rsq(x);
-  double s = x * r, h = 0.5 * r;
-  const double e = fma(-h, s, 0.5);
+  s = x * r;
+  h = 0.5 * r;
+  double e = fma(-h, s, 0.5);
   s = fma(s, e, s);
   h = fma(h, e, h);
-  s = fma(fma(-s, s, x), h, s);
-  return fma(fma(-s, s, x), h, s);
+  e = fma(-h, s, 0.5);
+  s = fma(s, e, s);
+  h = fma(h, e, h);
 }
-__device__ __forceinline__ float sqrt_nr(float x) { return sqrtf(x); }
-__device__ __forceinline__ float div_nr(float a, float x) { return a * __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ void sqrt_rsq(float x, float& s, float& h) {
+  const float r = __builtin_amdgcn_rsqf(x);
+  s = x * r;
+  h = 0.5f * r;
+  const float e = fmaf(-h, s, 0.5f);
+  s = fmaf(s, e, s);
+  h = fmaf(h, e, h);
+}
 
 // alpha_k / d_k = (L + Gamma_k)^q (eq:weights_unnormalized), Gamma_k =
 // (tau / b)^p (eq:weight_nonlinear), b = beta_k + eps mu^2 on the common
@@ -325,19 +334,20 @@ __device__ __forceinline__ T split_pair(const T (&w)[2 * R], const T (&g)[2 * R]
 // frame (component 1 = normal momentum, component 2 = tangential momentum).
 // Records live in LDS as structure of arrays, field f of a cell at
 // rec[f * fs + offset].
-//   Euler M = 4: rho, m_n, m_t, E, F1, F2, F3, sqrt(rho)   (8)
-//   Euler M = 3: rho, m_n, E, F1, F2, sqrt(rho)            (6)
-//   scalar:      u, f(u)                                  (2)
-// (F0 = m_n is not stored; the Roe ingredients 1/rho and H of the two cells
-// next to an interface are recomputed there, which keeps the LDS ring of the
-// y-sweep small enough for three blocks per compute unit.)
+//   Euler M = 4: rho, m_n, m_t, E, F1, F2, F3, 1/sqrt(rho)   (8)
+//   Euler M = 3: rho, m_n, E, F1, F2, 1/sqrt(rho)            (6)
+//   scalar:      u, f(u)                                    (2)
+// (F0 = m_n is not stored; the Roe ingredients sqrt(rho) u and sqrt(rho) H
+// of the two cells next to an interface are recomputed there from the
+// state and 1/sqrt(rho), which keeps the LDS ring of the y-sweep small
+// enough for three blocks per compute unit.)
 // ---------------------------------------------------------------------------
 template <int M> struct RecLayout;
 template <> struct RecLayout<4> {
-  enum { NF = 8, Q0 = 0, Q1 = 1, Q2 = 2, E = 3, F1 = 4, F2 = 5, F3 = 6, SR = 7 };
+  enum { NF = 8, Q0 = 0, Q1 = 1, Q2 = 2, E = 3, F1 = 4, F2 = 5, F3 = 6, RS = 7 };
 };
 template <> struct RecLayout<3> {
-  enum { NF = 6, Q0 = 0, Q1 = 1, Q2 = -1, E = 2, F1 = 3, F2 = -1, F3 = 4, SR = 5 };
+  enum { NF = 6, Q0 = 0, Q1 = 1, Q2 = -1, E = 2, F1 = 3, F2 = -1, F3 = 4, RS = 5 };
 };
 
 // Build the record of one Euler cell from its (frame-permuted) state.
@@ -346,7 +356,10 @@ __device__ __forceinline__ void euler_record(const double (&qd)[M], T gm1, T* re
   typedef RecLayout<M> Lo;
   const T q0 = (T)qd[0], q1 = (T)qd[1], E = (T)qd[M - 1];
   const T q2 = M == 4 ? (T)qd[M == 4 ? 2 : 0] : T(0);
-  const T ir = rcp_nr(q0);
+  T sq, hr;
+  sqrt_rsq(q0, sq, hr);
+  const T r = hr + hr;          // 1/sqrt(rho)
+  const T ir = r * r;           // 1/rho
   const T un = q1 * ir;
   T ke;
   if (M == 4) {
@@ -364,27 +377,27 @@ __device__ __forceinline__ void euler_record(const double (&qd)[M], T gm1, T* re
     rec[Lo::Q2 * fs] = q2;
     rec[Lo::F2 * fs] = q2 * un;
   }
-  rec[Lo::SR * fs] = sqrt_nr(q0);
+  rec[Lo::RS * fs] = r;
 }
 
-// Velocities and total enthalpy of one record (the Roe ingredients).
+// The Roe ingredients of one record: sqrt(rho) u_n = m_n r, sqrt(rho) u_t =
+// m_t r and sqrt(rho) H = (E + p) r with r = 1/sqrt(rho) and
+// p = (gamma-1) (E - ((sqrt(rho) u_n)^2 + (sqrt(rho) u_t)^2)/2).
 template <class T, int M>
-__device__ __forceinline__ void roe_side(const T* __restrict__ rec, int fs, int o, T gm1, T& un, T& ut, T& H) {
+__device__ __forceinline__ void roe_side(const T* __restrict__ rec, int fs, int o, T gm1, T& an, T& at, T& hs) {
   typedef RecLayout<M> Lo;
-  const T q0 = rec[Lo::Q0 * fs + o], q1 = rec[Lo::Q1 * fs + o], E = rec[Lo::E * fs + o];
-  const T ir = rcp_nr(q0);
-  un = q1 * ir;
+  const T q1 = rec[Lo::Q1 * fs + o], E = rec[Lo::E * fs + o], r = rec[Lo::RS * fs + o];
+  an = q1 * r;
   T ke;
   if (M == 4) {
-    const T q2 = rec[(M == 4 ? Lo::Q2 : 0) * fs + o];
-    ut = q2 * ir;
-    ke = fma(un, q1, ut * q2);
+    at = rec[(M == 4 ? Lo::Q2 : 0) * fs + o] * r;
+    ke = fma(an, an, at * at);
   } else {
-    ut = T(0);
-    ke = un * q1;
+    at = T(0);
+    ke = an * an;
   }
   const T p = gm1 * fma(T(-0.5), ke, E);
-  H = (E + p) * ir;
+  hs = (E + p) * r;
 }
 
 // ---------------------------------------------------------------------------
@@ -410,20 +423,22 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
                                            const T (&alpha)[M], const WeightCfg<T>& cfg, T (&Fh)[M]) {
   typedef RecLayout<M> Lo;
 #define ZA_R(f, j) rec[(f) * fs + off[j]]
-  // Roe average of the cells R-1 (= i) and R (= i+1) of the stencil
-  const T sl = ZA_R(Lo::SR, R - 1), sr = ZA_R(Lo::SR, R);
-  const T iw = rcp_nr(sl + sr);
-  const T wl = sl * iw, wr = sr * iw;
-  T unl, utl, Hl, unr, utr, Hr;
-  roe_side<T, M>(rec, fs, off[R - 1], gm1, unl, utl, Hl);
-  roe_side<T, M>(rec, fs, off[R], gm1, unr, utr, Hr);
-  const T u = fma(wl, unl, wr * unr);
-  const T v = M == 4 ? fma(wl, utl, wr * utr) : T(0);
-  const T H = fma(wl, Hl, wr * Hr);
+  // Roe average of the cells R-1 (= i) and R (= i+1) of the stencil:
+  // u = (sqrt(rho_l) u_l + sqrt(rho_r) u_r) / (sqrt(rho_l) + sqrt(rho_r)),
+  // likewise v and H, with 1/(sqrt(rho_l) + sqrt(rho_r)) = r_l r_r / (r_l + r_r)
+  const T rl = ZA_R(Lo::RS, R - 1), rr = ZA_R(Lo::RS, R);
+  const T iw = (rl * rr) * rcp_nr(rl + rr);
+  T anl, atl, hsl, anr, atr, hsr;
+  roe_side<T, M>(rec, fs, off[R - 1], gm1, anl, atl, hsl);
+  roe_side<T, M>(rec, fs, off[R], gm1, anr, atr, hsr);
+  const T u = (anl + anr) * iw;
+  const T v = M == 4 ? (atl + atr) * iw : T(0);
+  const T H = (hsl + hsr) * iw;
   const T q2 = T(0.5) * fma(u, u, v * v);
   const T c2 = gm1 * (H - q2);
-  const T c = sqrt_nr(c2);
-  const T ic = rcp_nr(c);
+  T c, hc;
+  sqrt_rsq(c2, c, hc);          // c and 1/(2c)
+  const T ic = hc + hc;
   const T b1 = gm1 * (ic * ic);
   const T k1 = gm1 * ic;
   // project the stencil onto the characteristic fields.  With
@@ -466,18 +481,28 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
     }
   }
 #undef ZA_R
+  // The FP64 kernels with the paper's Z weights run only for eps <= 1e-40
+  // (larger eps takes the general kernels): there the unscaled eps, an
+  // effective eps / (4 c^2) on the unscaled fields, moves a reconstruction
+  // by at most ~2e-13 of the stencil's scale, and the kernels keep the
+  // registers the per-interface eps would take.
+  constexpr bool scale_eps = !(WV == WV_Z1 && sizeof(T) == sizeof(double));
   WeightCfg<T> cfg_ac = cfg;
-  if (WV == WV_GENERAL && cfg.ai) {
-    cfg_ac.mu0x2 = cfg.mu0x2 * (c + c);
-  } else {
-    const T s2 = T(4) * c2;
-    cfg_ac.eps16 = cfg.eps16 * s2;
-    cfg_ac.eps4 = cfg.eps4 * s2;
+  if (scale_eps) {
+    if (WV == WV_GENERAL && cfg.ai) {
+      cfg_ac.mu0x2 = cfg.mu0x2 * (c + c);
+    } else {
+      const T s2 = T(4) * c2;
+      cfg_ac.eps16 = cfg.eps16 * s2;
+      cfg_ac.eps4 = cfg.eps4 * s2;
+    }
   }
+  // the two acoustic fields first, so that their epsilon dies early
   T gh[M];
+  gh[0] = split_pair<T, WV, R>(W[0], G[0], alpha[0], cfg_ac);
+  gh[M - 1] = split_pair<T, WV, R>(W[M - 1], G[M - 1], alpha[M - 1], cfg_ac);
 #pragma unroll
-  for (int s = 0; s < M; ++s)
-    gh[s] = split_pair<T, WV, R>(W[s], G[s], alpha[s], (s == 0 || s == M - 1) ? cfg_ac : cfg);
+  for (int s = 1; s < M - 1; ++s) gh[s] = split_pair<T, WV, R>(W[s], G[s], alpha[s], cfg);
   // back-projection F = R g, the acoustic fluxes unscaled by 1/(2c):
   // gh_0 + gh_3 = (gh'_0 + gh'_3)/(2c), c (gh_3 - gh_0) = (gh'_3 - gh'_0)/2
   const T s03 = (gh[0] + gh[M - 1]) * (T(0.5) * ic);

@@ -49,9 +49,15 @@ inline int order_of(const za_problem& p) { return p.order == 0 ? 3 : p.order; }
 inline double weight_L(const za_problem& p) { return p.weight_L == 0.0 && p.weight_q == 0.0 ? 1.0 : p.weight_L; }
 inline double weight_q(const za_problem& p) { return p.weight_L == 0.0 && p.weight_q == 0.0 ? 1.0 : p.weight_q; }
 
+// FP64 Z-weight kernels apply eps unscaled to the characteristic fields they
+// carry scaled (Euler's acoustic fields, by 2c); that is exact to ~2e-13 of
+// a stencil's scale only for eps up to the paper's 1e-40, so a larger eps
+// takes the general kernels, which scale it.
+constexpr double kEpsFastMax = 1e-40;
+
 inline bool general_weights(const za_problem& p) {
   return p.p != 1.0 || p.affine_invariant || p.linear_weights || p.alt_tau || weight_L(p) != 1.0 ||
-         weight_q(p) != 1.0;
+         weight_q(p) != 1.0 || (p.precision == ZA_FP64 && p.eps > kEpsFastMax);
 }
 
 template <class T>

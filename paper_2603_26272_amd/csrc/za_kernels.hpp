@@ -97,10 +97,11 @@ __device__ __forceinline__ double wave_max(double a, double b) { return a > b ? 
 // Velocities and sound speed of one Euler cell, each operation rounded once
 // in the order u = m_x / rho, v = m_y / rho,
 // p = (gamma-1) (E - (rho/2) (u^2 + v^2)), c^2 = gamma p / rho, c = sqrt(c^2),
-// with IEEE division and square root and no contraction: the wave speeds,
-// hence the Lax-Friedrichs speeds of eq:LF and the CFL step, are then exact
-// functions of the state that any other correctly rounded evaluation in this
-// order reproduces bit for bit.  Runs once per cell and stage.
+// with correctly rounded division and square root and no contraction: the
+// wave speeds, hence the Lax-Friedrichs speeds of eq:LF and the CFL step,
+// are then exact functions of the state that any other correctly rounded
+// evaluation in this order reproduces bit for bit.  Runs once per cell and
+// stage.
 __device__ __forceinline__ void euler_cell_speed(double rho, double mx, double my, double E, const Phys& ph,
                                                  double& u, double& v, double& p, double& c2) {
 #pragma clang fp contract(off)
@@ -751,7 +752,7 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
   const bool xin = x < nx;
   const int kend = ylast;                    // interfaces y0 .. kend
   const size_t cs = (size_t)nx * ny;
-  const double* col = a.q + (xin ? x : 0);
+  const int xc = xin ? x : 0;   // column offset of this lane's loads
   T* const rw = &ring[wv][cl];
   double(*const fw)[M][YS_COLS] = fb[wv];
   // Ring slot of cell row r is (r - y0 + R) mod YS_RING; flux slot of
@@ -764,7 +765,8 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
 #pragma unroll
     for (int t = 0; t < NPRO; ++t) {
       const int i = g + YS_ROWS * t;
-      if (xin && i < YS_RING) cell_load<SYS, M, 1>(col, cs, (size_t)bc_map(y0 - R + i, ny, a.g.bc_y) * nx, qr[t]);
+      if (xin && i < YS_RING)
+        cell_load<SYS, M, 1>(a.q, cs, (size_t)bc_map(y0 - R + i, ny, a.g.bc_y) * nx + xc, qr[t]);
     }
 #pragma unroll
     for (int t = 0; t < NPRO; ++t) {
@@ -793,7 +795,7 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
     if (need) {
       const size_t off = (size_t)bc_map(rn, ny, a.g.bc_y) * nx;
 #pragma unroll
-      for (int c = 0; c < M; ++c) qp[c] = col[off + c * cs];
+      for (int c = 0; c < M; ++c) qp[c] = a.q[off + xc + c * cs];
     }
     const int r = k - 1;   // cell row finished by this lane
     const bool upd = MODE != MODE_FLUX && act && r >= y0 && r < ylast;

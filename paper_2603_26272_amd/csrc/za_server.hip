@@ -705,8 +705,7 @@ za_status za_server_submit(za_server* sv, const za_problem* p, const double* q0,
     if (vs != ZA_OK) return vs;
   }
   // batches run the paper's weights (Z type, p = 1, mu = 1) on the Euler equations
-  if (p->system != ZA_EULER || p->p != 1.0 || p->affine_invariant || p->linear_weights || order_of(*p) != 3 ||
-      p->pp_limiter || p->alt_tau || weight_L(*p) != 1.0 || weight_q(*p) != 1.0)
+  if (p->system != ZA_EULER || general_weights(*p) || order_of(*p) != 3 || p->pp_limiter)
     return ZA_ERR_UNSUPPORTED;
   int sb, xb, ys, yb, xc;
   if (footprint(*p, &sb, &xb, &ys, &yb, &xc) > sv->budget) return ZA_ERR_NOMEM;

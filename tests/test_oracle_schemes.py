@@ -287,9 +287,10 @@ def test_config3_400_oracle_step_count_near_paper(orc):
     oracle only; 16 minutes on 7 threads) takes 3554 steps with the summed 2D
     rule dt = CFL / (max(|u|+c)/dx + max(|v|+c)/dy): 1.6 % more.  The paper
     states no 2D rule; the per-direction rule CFL dx / max(|u|+c, |v|+c)
-    would take about half as many steps and the per-cell maximum of
-    (|u|+c)/dx + (|v|+c)/dy about 20 % fewer at t = 0, so the summed rule is
-    the reading, within 2 % of the printed count.  The stored record must
+    would take about half as many steps, and the per-cell maximum
+    CFL / max((|u|+c)/dx + (|v|+c)/dy) took 3416 (2.3 % fewer, measured with
+    a scratch copy of the oracle), so the summed rule is the reading, within
+    2 % of the printed count.  The stored record must
     come from this oracle: its first dt is recomputed here bit for bit."""
     gold = _config3_golden()
     P, q0, T = W.riemann_config3(400)
