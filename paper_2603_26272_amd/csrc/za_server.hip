@@ -37,7 +37,7 @@ using namespace za;
 
 constexpr int MAX_SLOTS = 256;  // per class
 constexpr int NCLASS = 4;       // (1D, 2D) x (FP64, FP32 reconstruction)
-constexpr int SERVE_YTILE = 8 * YS_ROWS - 1; // y-sweep rows per block in batches (a whole number of steps)
+constexpr int SERVE_YTILE = 8 * YS_ROWS - 1; // default y-sweep rows per block in batches (a whole number of steps)
 
 struct SlotDesc {
   double* st;        // the request's state (Q^n, then the result)
@@ -54,6 +54,7 @@ struct SlotDesc {
   int yblocks;       // y-sweep blocks (strips x tiles)
   int stage_blocks;  // rows of wave-speed maxima the kernel that writes a stage state leaves
   int xl_chunks;     // FP64: chunks per segment of the looped x-sweep
+  int ytile;         // 2D: y-sweep rows per block (band height)
 };
 
 struct BatchTable {
@@ -84,7 +85,7 @@ __device__ __forceinline__ SweepArgs slot_args(const SlotDesc& d, int stage, boo
   a.ca = stage == 0 ? 0.0 : (stage == 1 ? 0.75 : 1.0 / 3.0);
   a.cb = stage == 0 ? 1.0 : (stage == 1 ? 0.25 : 2.0 / 3.0);
   a.check_active = 1;
-  a.ytile = SERVE_YTILE;
+  a.ytile = d.ytile;
   a.part = d.part;
   a.xl_chunks = d.xl_chunks;
   return a;
@@ -145,8 +146,9 @@ __global__ __launch_bounds__(256, ZA_YS_WAVES) void kb_sweep_y(const BatchTable*
   const SweepArgs a = slot_args(d, stage, false);
   const CfgArg<T> cfg = slot_cfg<T>(d);
   const int local = b - tab->yoff[s];
-  sweep_y_body<SYS_EULER, 4, T, MODE_STAGE, WV_Z1, 3, 0, false>(a, cfg, local % d.ystrips, local / d.ystrips,
-                                                                 d.ystrips);
+  // FP32 records leave room for the partial stage's early loads; FP64 would spill
+  sweep_y_body<SYS_EULER, 4, T, MODE_STAGE, WV_Z1, 3, 0, sizeof(T) == sizeof(float)>(a, cfg, local % d.ystrips,
+                                                                                    local / d.ystrips, d.ystrips);
 }
 
 __global__ __launch_bounds__(64) void kb_final(const BatchTable* __restrict__ tab, int kind, int dim) {
@@ -292,31 +294,64 @@ struct za_server {
   // (ZA_SRV_FAIL_BURST=k: the k-th burst launch reports a launch error)
   int64_t fail_burst = 0, bursts = 0;
   bool graphs = true;   // replay a captured graph per class step (ZA_SRV_GRAPHS=0: direct launches)
+  int64_t max_burst = SERVE_MAX_BURST;   // ZA_SRV_BURST overrides (1 .. 64)
 };
+
+constexpr long long kServeMinWaves = 3072;   // 3 per SIMD of a 256-CU device
 
 // Chunks per segment of the looped x-sweep, which FP64 requests always use
 // (0 for FP32 reconstruction: the one-shot sweep), fixed at admission (its
-// wave-speed rows depend on it in 1D): segments of about a quarter row in 2D
-// and of up to 4 chunks in 1D keep many wavefronts per request.
-// ZA_SRV_XL_CHUNKS in the environment forces a value, clamped to 1 .. 64.
+// wave-speed rows depend on it in 1D).  2D: the count that minimises the
+// work of a row, segments x (chunks + 0.15 for a segment's start), since a
+// row of n cells takes ceil(n / (64 nc - 1)) segments and a last segment of a
+// few cells costs as much as a full one (n = 1024: 3 chunks, 6 segments,
+// instead of 4 chunks, 5 segments), among the counts that leave a request
+// at least kServeMinWaves wavefronts (its latency when alone).  1D: up to
+// 4 chunks, which keeps many
+// wavefronts per request.  ZA_SRV_XL_CHUNKS in the environment forces a
+// value, clamped to 1 .. 64.
 static int serve_xl_chunks(const za_problem& p) {
   if (p.precision != ZA_FP64) return 0;
   if (const char* e = std::getenv("ZA_SRV_XL_CHUNKS")) return std::max(1, std::min(std::atoi(e), 64));
-  const int nc = p.dim == 2 ? p.nx / 256 : p.nx / 2048;
-  return std::max(1, std::min(4, nc));
+  if (p.dim == 1) return std::max(1, std::min(4, p.nx / 2048));
+  int best = 1;
+  double best_cost = -1.0;
+  for (int nc = 1; nc <= 16; ++nc) {
+    const long long seg = 64LL * nc - 1;
+    const long long segs = (p.nx + seg - 1) / seg;
+    // a request alone still fills three wavefronts per SIMD where it can
+    if (nc > 1 && (long long)p.ny * segs < kServeMinWaves) break;
+    const double cost = (double)segs * (nc + 0.15);
+    if (best_cost < 0.0 || cost < best_cost) { best_cost = cost; best = nc; }
+    if (seg >= p.nx) break;   // one segment per row from here on
+  }
+  return best;
+}
+
+// Rows per y-sweep block of a 2D request, fixed at admission:
+// SERVE_YTILE, or ZA_SRV_YTILE from the environment (rounded to a whole
+// number of YS_ROWS-row steps, at least one).
+static int serve_ytile(const za_problem& p) {
+  (void)p;
+  if (const char* e = std::getenv("ZA_SRV_YTILE")) {
+    const int v = std::max(1, std::atoi(e) / YS_ROWS);
+    return YS_ROWS * std::min(v, 256) - 1;
+  }
+  return SERVE_YTILE;
 }
 
 static size_t footprint(const za_problem& p, int* stage_blocks, int* xblocks, int* ystrips, int* yblocks,
-                        int* xl_chunks) {
+                        int* xl_chunks, int* ytile) {
   const int m = ncomp(p);
   const size_t S = (size_t)m * p.nx * p.ny * sizeof(double);
   *xl_chunks = serve_xl_chunks(p);
+  *ytile = serve_ytile(p);
   const long long xw = *xl_chunks > 0 ? xl_waves(p.nx, p.ny, *xl_chunks)
                                       : (long long)p.ny * ((p.nx + XS_CELLS - 1) / XS_CELLS);
   *xblocks = (int)((xw + 3) / 4);
   if (p.dim == 2) {
     *ystrips = (p.nx + 63) / 64;
-    *yblocks = *ystrips * ((p.ny + SERVE_YTILE - 1) / SERVE_YTILE);
+    *yblocks = *ystrips * ((p.ny + *ytile - 1) / *ytile);
     *stage_blocks = *yblocks;
   } else {
     *ystrips = 0;
@@ -445,8 +480,8 @@ static void admit(za_server* sv, std::unique_lock<std::mutex>& lk) {
     Class& C = sv->cls[r->cls];
     if (total >= sv->max_slots) break;
     if (C.free_slots.empty()) { ++it; continue; }
-    int sb, xb, ys, yb, xc;
-    const size_t need = footprint(r->prob, &sb, &xb, &ys, &yb, &xc);
+    int sb, xb, ys, yb, xc, yt;
+    const size_t need = footprint(r->prob, &sb, &xb, &ys, &yb, &xc, &yt);
     size_t off;
     if (!sv->pool.alloc(need, &off)) { ++it; continue; }
     r->off = off;
@@ -474,7 +509,7 @@ static void admit(za_server* sv, std::unique_lock<std::mutex>& lk) {
     d.ph.cfl = p.cfl; d.ph.dt_rule = p.dt_rule; d.ph.lf_scalar = p.lf == ZA_LF_SCALAR ? 1 : 0;
     d.ph.pp = 0;   // requests with the limiter are not admitted
     d.eps16 = 16.0 * p.eps; d.eps4 = 4.0 * p.eps; d.mu0x2 = 2.0 * p.mu0;
-    d.xblocks = xb; d.ystrips = ys; d.yblocks = yb; d.stage_blocks = sb; d.xl_chunks = xc;
+    d.xblocks = xb; d.ystrips = ys; d.yblocks = yb; d.stage_blocks = sb; d.xl_chunks = xc; d.ytile = yt;
     picked.push_back(r);
     ++total;
     it = sv->waiting.erase(it);
@@ -546,7 +581,7 @@ static void launch_burst(za_server* sv, int c) {
   }
   int64_t burst = 1;
   for (const Req* r : C.active) burst = std::max(burst, r->n_steps - r->launched);
-  burst = std::min<int64_t>(burst, SERVE_MAX_BURST);
+  burst = std::min<int64_t>(burst, sv->max_burst);
   ++sv->bursts;
   if (sv->fail_burst > 0 && sv->bursts == sv->fail_burst) {
     fail_class(sv, c, "graph launch failed (injected)");
@@ -665,6 +700,7 @@ za_status za_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t d
   sv->device = device;
   if (const char* e = std::getenv("ZA_SRV_FAIL_BURST")) sv->fail_burst = std::atoll(e);
   if (const char* e = std::getenv("ZA_SRV_GRAPHS")) sv->graphs = std::atoi(e) != 0;
+  if (const char* e = std::getenv("ZA_SRV_BURST")) sv->max_burst = std::max(1, std::min(std::atoi(e), 64));
   if (hipSetDevice(device) != hipSuccess) return fail(ZA_ERR_DEVICE);
   void* p = nullptr;
   if (hipMalloc(&p, hbm_budget_bytes) != hipSuccess) return fail(ZA_ERR_NOMEM);
@@ -707,8 +743,8 @@ za_status za_server_submit(za_server* sv, const za_problem* p, const double* q0,
   // batches run the paper's weights (Z type, p = 1, mu = 1) on the Euler equations
   if (p->system != ZA_EULER || general_weights(*p) || order_of(*p) != 3 || p->pp_limiter)
     return ZA_ERR_UNSUPPORTED;
-  int sb, xb, ys, yb, xc;
-  if (footprint(*p, &sb, &xb, &ys, &yb, &xc) > sv->budget) return ZA_ERR_NOMEM;
+  int sb, xb, ys, yb, xc, yt;
+  if (footprint(*p, &sb, &xb, &ys, &yb, &xc, &yt) > sv->budget) return ZA_ERR_NOMEM;
   auto r = std::make_unique<Req>();
   r->prob = *p;
   r->cls = class_of(*p);
