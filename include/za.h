@@ -77,9 +77,11 @@ typedef struct {
   int32_t dt_rule;         /* za_dt_rule                                     */
   int32_t precision;       /* za_precision                                   */
   double  p;               /* power parameter of eq:weight_nonlinear (1)     */
-  double  eps;             /* sensitivity epsilon (1e-40 FP64, 1e-20 FP32)   */
+  double  eps;             /* sensitivity epsilon (1e-40 FP64, 1e-20 FP32);  */
+                           /* at least 1e-300 (FP64) or 1e-37 (FP32)         */
   int32_t affine_invariant;/* 0: mu = 1 (Section 3); 1: mu[f] of eq:aimu      */
-  double  mu0;             /* mu_0 of eq:aimu (1e-40 FP64, 1e-8 FP32)        */
+  double  mu0;             /* mu_0 of eq:aimu (1e-40 FP64, 1e-8 FP32);       */
+                           /* at least 1e-150 (FP64) or 1e-18 (FP32)         */
   int32_t lf;              /* za_lf                                          */
   int32_t linear_weights;  /* 1: omega = d (the linear central flux), tests  */
   int32_t order;           /* r of the order-2r central-upwind scheme: 3 (or  */

@@ -41,23 +41,21 @@ struct WeightCfg {
 // linear weights) decided at run time.
 enum { WV_Z1 = 0, WV_GENERAL = 1 };
 
-// Reciprocal from the hardware reciprocal estimate refined by two
-// Newton-Raphson steps (r <- r + r (1 - x r)); quotient from an estimate
-// refined once, then one residual correction (q <- q + r (a - x q)), which
-// squares the relative error of the once-refined reciprocal again (an
-// estimate good to 2^-14 already leaves only the final rounding).  Operands
-// stay far from the denormal and overflow ranges here (positive normal
-// densities and weight sums >= 1e-156), so no exponent scaling is needed.
+// The hardware FP64 reciprocal and reciprocal-square-root estimates are
+// good to a relative 2^-24 (measured over 4M normal operands on gfx950: at
+// most 4.6e-8 and 5.2e-8).  One refinement squares that error: the
+// reciprocal takes one Newton-Raphson step (r <- r + r (1 - x r)), the
+// quotient one residual correction of a r (q <- q + r (a - x q)), each
+// within about 2^-48 relative, three orders of magnitude inside the flux
+// tolerance of 1e-12.  Operands stay far from the denormal and overflow
+// ranges here (positive normal densities and weight sums >= 1e-276), so no
+// exponent scaling is needed.
 __device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
 }
 __device__ __forceinline__ double div_nr(double a, double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
+  const double r = __builtin_amdgcn_rcp(x);
   const double q = a * r;
   return fma(fma(-x, q, a), r, q);
 }
@@ -67,17 +65,14 @@ __device__ __forceinline__ float div_nr(float a, float x) { return a * __builtin
 
 // Square root s and half reciprocal square root h = 1/(2 sqrt(x)) of a
 // positive normal number together: the hardware reciprocal-square-root
-// estimate refined by coupled Goldschmidt iterations (e = 1/2 - h s,
-// s <- s + s e, h <- h + h e), each of which squares the relative error;
-// two suffice in FP64 (to about an ulp), one in FP32.
+// estimate refined by one coupled Goldschmidt iteration (e = 1/2 - h s,
+// s <- s + s e, h <- h + h e), which squares its relative error (to about
+// 2^-48 in FP64, the FP32 rounding in FP32).
 __device__ __forceinline__ void sqrt_rsq(double x, double& s, double& h) {
   const double r = __builtin_amdgcn_rsq(x);
   s = x * r;
   h = 0.5 * r;
-  double e = fma(-h, s, 0.5);
-  s = fma(s, e, s);
-  h = fma(h, e, h);
-  e = fma(-h, s, 0.5);
+  const double e = fma(-h, s, 0.5);
   s = fma(s, e, s);
   h = fma(h, e, h);
 }
@@ -144,8 +139,9 @@ __device__ __forceinline__ T z_alpha(T tau, T b, T bmin, const WeightCfg<T>& w) 
 //   b_k = B_k + 16 eps, P_k = prod_{j != k} b_j  (the 1/20 cancels),
 //   (b_k + T) P_k = P + T P_k with P = prod_j b_j,
 // algebraically identical to the normalised weights with one division
-// instead of five.  b_k >= 1.6e-39 keeps every product above 1e-156, so
-// nothing underflows; the products overflow only for flux values beyond
+// instead of five.  These kernels run for 1e-70 <= eps <= 1e-40, so
+// b_k >= 1.6e-69 keeps every product above 6e-276 and nothing underflows
+// (a smaller eps takes the general kernels); the products overflow only for flux values beyond
 // about 1e37, and the resulting non-finite state is reported.  FP32 keeps the
 // direct form (three indicators at 16 eps_32 would underflow) with the
 // hardware reciprocal.

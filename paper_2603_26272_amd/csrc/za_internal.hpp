@@ -52,12 +52,17 @@ inline double weight_q(const za_problem& p) { return p.weight_L == 0.0 && p.weig
 // FP64 Z-weight kernels apply eps unscaled to the characteristic fields they
 // carry scaled (Euler's acoustic fields, by 2c); that is exact to ~2e-13 of
 // a stencil's scale only for eps up to the paper's 1e-40, so a larger eps
-// takes the general kernels, which scale it.
+// takes the general kernels, which scale it.  They also form products of
+// four indicators, which for a flat stencil are (16 eps)^4: below
+// kEpsFastMin that product leaves the normal range (at eps ~ 1e-82 it is
+// zero and the weights 0/0), so a smaller eps takes the general kernels too,
+// which divide per indicator.
 constexpr double kEpsFastMax = 1e-40;
+constexpr double kEpsFastMin = 1e-70;
 
 inline bool general_weights(const za_problem& p) {
   return p.p != 1.0 || p.affine_invariant || p.linear_weights || p.alt_tau || weight_L(p) != 1.0 ||
-         weight_q(p) != 1.0 || (p.precision == ZA_FP64 && p.eps > kEpsFastMax);
+         weight_q(p) != 1.0 || (p.precision == ZA_FP64 && (p.eps > kEpsFastMax || p.eps < kEpsFastMin));
 }
 
 template <class T>

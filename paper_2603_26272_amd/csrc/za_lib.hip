@@ -56,6 +56,9 @@ za_status za_validate(const za_problem* p, std::string* why) {
   if (p->affine_invariant && !(p->mu0 > 0.0)) return fail("mu0 must be positive");
   if (p->precision == ZA_FP32_RECON && (p->eps < 1e-37 || (p->affine_invariant && p->mu0 < 1e-18)))
     return fail("FP32 reconstruction needs eps >= 1e-37 and mu0 >= 1e-18 (normal FP32 range)");
+  // 16 eps and (2 mu0)^2 must be normal FP64 numbers with a finite reciprocal
+  if (p->precision == ZA_FP64 && (p->eps < 1e-300 || (p->affine_invariant && p->mu0 < 1e-150)))
+    return fail("FP64 needs eps >= 1e-300 and mu0 >= 1e-150 (normal FP64 range)");
   if (p->order != 0 && (p->order < 2 || p->order > 5)) return fail("order r must be 2, 3, 4 or 5");
   if (p->pp_limiter != 0 && p->pp_limiter != 1) return fail("pp_limiter must be 0 or 1");
   if (p->alt_tau != 0 && p->alt_tau != 1) return fail("alt_tau must be 0 or 1");

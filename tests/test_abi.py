@@ -66,6 +66,21 @@ def test_option_validation_host_side():
         assert not ok(bad), bad
 
 
+def test_epsilon_range_host_side():
+    """16 eps and (2 mu_0)^2 must stay normal numbers with finite reciprocals
+    (eq:weight_nonlinear, eq:aimu): FP64 takes eps >= 1e-300 and mu_0 >=
+    1e-150, FP32 reconstruction eps >= 1e-37 and mu_0 >= 1e-18."""
+    from paper_2603_26272_amd import za
+    from paper_2603_26272_amd.problem import Problem
+    ok = lambda P: za.state_count(P) > 0
+    base = Problem(dim=1, nx=40)
+    assert ok(base.with_(eps=1e-300)) and ok(base.with_(eps=1e-100))
+    assert not ok(base.with_(eps=1e-301)) and not ok(base.with_(eps=0.0))
+    assert ok(base.with_(affine_invariant=1, mu0=1e-150))
+    assert not ok(base.with_(affine_invariant=1, mu0=1e-151))
+    assert ok(base.fp32().with_(eps=1e-37)) and not ok(base.fp32().with_(eps=1e-38))
+
+
 def test_problem_struct_layout_matches_header(tmp_path):
     """The binding's ctypes mirror of za_problem has the C layout (size and
     every field offset), checked with the host C compiler."""

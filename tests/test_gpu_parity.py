@@ -344,6 +344,23 @@ def test_solve_euler_2d(dev):
     assert_close(q.cpu().numpy(), ref, 1e-10, "2d solve")
 
 
+@pytest.mark.parametrize("eps", [1e-60, 1e-100, 1e-300])
+def test_solve_tiny_eps_on_flat_states(dev, eps):
+    """eq:weight_nonlinear with an epsilon far below the paper's 1e-40 on
+    Riemann data, whose constant regions give all-zero indicators: the
+    weights are then the linear ones, and the GPU steps match the oracle's.
+    (The fast kernels form products of four (16 eps) terms and run only down
+    to eps = 1e-70; smaller eps takes the general kernels.)"""
+    P, q0 = W.quadrants_2d(3, 96, 80)
+    P = P.with_(eps=eps)
+    q = torch.from_numpy(q0).to(dev)
+    with Ctx(P) as ctx:
+        info = ctx.solve(q, 0.0, 5)
+    ref, steps, t, st = orc.solve(P, q0, 0.0, 5)
+    assert st == 0 and info["steps"] == steps == 5
+    assert_close(q.cpu().numpy(), ref, 1e-10, f"eps {eps:g}")
+
+
 def test_solve_to_time_clips_last_step(dev):
     P, q0, T = W.shock_tube("sod", 200)
     q = torch.from_numpy(q0).to(dev)
