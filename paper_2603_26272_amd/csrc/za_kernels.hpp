@@ -111,6 +111,14 @@ __device__ __forceinline__ void euler_cell_speed(double rho, double mx, double m
   c2 = ph.gamma * p / rho;
 }
 
+// acc = max(acc, |x|) for numbers acc, x (no NaN): one v_max_f64 with the
+// absolute-value modifier, in place.  (fmax would make the compiler quiet
+// possible signalling NaNs first, an extra instruction per operand and
+// register copies around the loop that carries acc.)
+__device__ __forceinline__ void max_abs_into(double& acc, double x) {
+  asm("v_max_f64 %0, %0, |%1|" : "+v"(acc) : "v"(x));
+}
+
 template <int SYS, int M>
 __device__ __forceinline__ void cell_speeds(const double (&Q)[M], const Phys& ph, double (&r)[NPART]) {
   if (SYS == SYS_EULER) {
@@ -118,16 +126,20 @@ __device__ __forceinline__ void cell_speeds(const double (&Q)[M], const Phys& ph
     euler_cell_speed(Q[0], Q[1 % M], M == 4 ? Q[2 % M] : 0.0, Q[M - 1], ph, u, v, p, c2);
     // A NaN or infinite component makes p NaN, -inf or +inf (then c2 = +inf),
     // so these tests also reject every non-finite state; past them all
-    // speeds are numbers and fmax needs no NaN care.
+    // speeds are numbers and the maxima need no NaN care.  (A branch-free
+    // form with a select on r[0] saves a few instructions but led the
+    // compiler to reuse the registers of in-flight stores early, and the
+    // waits for those stores cost 7 % of the y-sweep.)
     const bool ok = Q[0] > 0.0 && p > 0.0 && c2 > 0.0 && c2 < __builtin_huge_val();
     if (!ok) { r[0] = __builtin_huge_val(); return; }
     const double c = __builtin_sqrt(c2);
-    r[0] = fmax(r[0], fabs(u - c));
-    r[1] = fmax(r[1], fabs(u));
-    r[2] = fmax(r[2], fabs(u + c));
-    r[3] = fmax(r[3], fabs(v - c));
-    r[4] = fmax(r[4], fabs(v));
-    r[5] = fmax(r[5], fabs(v + c));
+    max_abs_into(r[0], u - c);
+    max_abs_into(r[1], u);
+    max_abs_into(r[2], u + c);
+    max_abs_into(r[3], v - c);
+    max_abs_into(r[4], v);
+    max_abs_into(r[5], v + c);
+
   } else if (SYS == SYS_BUCKLEY) {
     // non-convex flux: keep the data range (max u, max -u); the final
     // reduction takes max |f'| over it
@@ -573,6 +585,10 @@ __host__ __device__ constexpr long long xl_waves(int nx, int ny, int nc) {
 
 __device__ __forceinline__ int xl_slot(int k) { return k & (XL_RING - 1); }
 
+// Write-only target of the looped sweep's lanes that have no cell to store
+// (component c of lane l at [64 c + l]); nothing reads it.
+static __device__ double xl_sink[4 * 64];
+
 template <int SYS, int M>
 __device__ __forceinline__ void xl_load(const double* __restrict__ row, size_t cs, int j, double (&qp)[M]) {
 #pragma unroll
@@ -638,13 +654,11 @@ __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<d
     xl_load<SYS, M>(rowq, cs, bc_map(s0 - R + lane, nx, bcx), q0);
     xl_load<SYS, M>(rowq, cs, bc_map(s0 - R + 64 + lane, nx, bcx), qp);
     xl_record<SYS, M>(q0, a.ph, ring + lane);
+    xl_record<SYS, M>(qp, a.ph, ring + xl_slot(64 + lane));
   }
   for (int j = 0; j < nch; ++j) {
     const int I0 = s0 + 64 * j;
-    // the 64 cells this chunk adds: I0 + 64 - R + lane, over the slots of
-    // cells I0 - 64 - R + lane, which the previous chunk was the last to read
-    xl_record<SYS, M>(qp, a.ph, ring + xl_slot(64 * j + 64 + lane));
-    wave_sync();
+    wave_sync();   // the records of cells I0 - R .. I0 + 124 - R are in the ring
     if (j + 1 < nch) xl_load<SYS, M>(rowq, cs, bc_map(I0 + 128 - R + lane, nx, bcx), qp);
     // the cell this lane completes, and its Q^n (fetched before the fluxes)
     const int i = I0 - 1 + lane;
@@ -667,8 +681,15 @@ __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<d
       for (int c = 0; c < M; ++c) fw[c][lane + 1] = F[c];
     }
     wave_sync();
-    if (upd) {
+    {
+      // Every lane stores, those without a cell of their own (the first
+      // lane of the first chunk, whose cell the previous segment completes,
+      // and lanes past the row's end) into xl_sink: with no branch around
+      // the stores, each chunk issues the same memory operations, and the
+      // wait for the next chunk's cells below never waits for these stores.
       const int si = xl_slot(64 * j + lane - 1 + R);
+      double* d = upd ? a.out + (size_t)line * nx + i : xl_sink + lane;
+      const size_t dstride = upd ? cs : 64;
       double qnew[M];
 #pragma unroll
       for (int c = 0; c < M; ++c) {
@@ -683,15 +704,19 @@ __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<d
         const double Fm = lane == 0 ? fw[c][65] : fw[c][lane];
         const double L = -(fw[c][lane + 1] - Fm) * a.g.inv_dx;
         qnew[c] = fma(a.ca, qb[c], a.cb * fma(sk.dt, L, qc));
-        a.out[c * cs + (size_t)line * nx + i] = qnew[c];
+        *d = qnew[c];
+        d += dstride;
       }
-      if (MODE == MODE_STAGE) cell_speeds<SYS, M>(qnew, a.ph, rs);
+      if (MODE == MODE_STAGE && upd) cell_speeds<SYS, M>(qnew, a.ph, rs);
     }
     wave_sync();
     if (lane == 63 && I <= nx) {
 #pragma unroll
       for (int c = 0; c < M; ++c) fw[c][65] = fw[c][64];
     }
+    // the 64 cells the next chunk adds, I0 + 128 - R + lane, over the slots
+    // of cells I0 - R + lane, which this chunk was the last to read
+    if (j + 1 < nch) xl_record<SYS, M>(qp, a.ph, ring + xl_slot(64 * j + 128 + lane));
   }
   if (MODE == MODE_STAGE && a.part) wave_max_store(rs, a.part + (size_t)wid * NPART);
 }
@@ -825,6 +850,26 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
       }
     }
     wave_sync();
+    if (need) {
+      // row rn takes the slot of row rn - YS_RING = k0 - R + g, which only
+      // this step's stencils (above the synchronisation) read.  Built
+      // before the update's stores: waiting for the loaded row then never
+      // waits for stores.
+      T* rec = rw + sb;
+      if (SYS == SYS_EULER) {
+        double qd[M];
+        if (M == 4) { qd[0] = qp[0]; qd[1] = qp[2 % M]; qd[2 % M] = qp[1]; qd[3 % M] = qp[3 % M]; }
+        else {
+#pragma unroll
+          for (int c = 0; c < M; ++c) qd[c] = qp[c];
+        }
+        euler_record<T, (M == 1 ? 4 : M)>(*reinterpret_cast<const double(*)[(M == 1 ? 4 : M)]>(qd), (T)a.ph.gm1, rec, YS_COLS);
+      } else {
+        const T u = (T)qp[0];
+        rec[0] = u;
+        rec[YS_COLS] = scalar_f<SYS, T>(u, (T)a.ph.adv[1]);
+      }
+    }
     if (upd) {
       double qnew[M];
       if (!LXPRE) {
@@ -843,24 +888,6 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
         }
       }
       if (MODE == MODE_STAGE) cell_speeds<SYS, M>(qnew, a.ph, rs);
-    }
-    if (need) {
-      // row rn takes the slot of row rn - YS_RING = k0 - R + g, which only
-      // this step's stencils (above the synchronisation) read
-      T* rec = rw + sb;
-      if (SYS == SYS_EULER) {
-        double qd[M];
-        if (M == 4) { qd[0] = qp[0]; qd[1] = qp[2 % M]; qd[2 % M] = qp[1]; qd[3 % M] = qp[3 % M]; }
-        else {
-#pragma unroll
-          for (int c = 0; c < M; ++c) qd[c] = qp[c];
-        }
-        euler_record<T, (M == 1 ? 4 : M)>(*reinterpret_cast<const double(*)[(M == 1 ? 4 : M)]>(qd), (T)a.ph.gm1, rec, YS_COLS);
-      } else {
-        const T u = (T)qp[0];
-        rec[0] = u;
-        rec[YS_COLS] = scalar_f<SYS, T>(u, (T)a.ph.adv[1]);
-      }
     }
     wave_sync();
     // advance by YS_ROWS rows (YS_ROWS < YS_RING, YS_ROWS < YS_FSLOT)
