@@ -227,7 +227,8 @@ za_status za_ctx_kernel_times(za_ctx* ctx, double* avg_ms, int64_t* counts);
 /* and a slot is free; every scheduler step advances all admitted requests */
 /* by one RK3 step with batched launches (one launch per kernel class for  */
 /* all slots, dispatched through a device slot table), retires finished    */
-/* requests and admits waiting ones.  The server owns a scheduler thread.  */
+/* requests and admits waiting ones.  The server owns a scheduler thread   */
+/* and a transfer thread (uploads and result downloads).                   */
 /* ---------------------------------------------------------------------- */
 typedef struct za_server za_server;
 typedef int64_t za_req_id;
@@ -239,7 +240,8 @@ typedef struct {
 } za_req_stats;
 
 /* Not from the paper.  hbm_budget_bytes: cap on the summed footprint of
- * admitted requests (the server allocates one pool of that size).
+ * admitted requests (the server allocates one pool of that size, and a
+ * pinned host staging pool of the same size, at most 1 GiB).
  * max_slots: concurrent requests.  device: HIP device ordinal.  *out
  * receives the server (NULL on error). */
 za_status za_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t device, za_server** out);

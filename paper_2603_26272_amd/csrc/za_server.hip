@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
@@ -215,7 +216,12 @@ struct Req {
   za_problem prob;
   int cls = 0, m = 1;
   size_t ncell = 0;
-  std::vector<double> q0, qout;
+  std::vector<double> q0;           // initial state until its upload (no pinned space)
+  std::unique_ptr<double[]> qout;   // final state after its download (no pinned space)
+  double* h_in = nullptr;           // initial state in the pinned staging pool
+  double* h_out = nullptr;          // final state in the pinned staging pool
+  size_t h_in_off = 0, h_out_off = 0;
+  bool xfer_ok = false;             // result of the last transfer
   int64_t n_steps = 0;
   int64_t t_arr = 0, t_adm = 0, t_fin = 0;
   int status = ZA_OK;
@@ -236,6 +242,13 @@ struct Burst {
   std::vector<Req*> members;
 };
 
+// A transfer for the transfer thread: the initial state of an admitted
+// request (up) or the final state of a finished one.
+struct XJob {
+  Req* r;
+  bool up;
+};
+
 // RK3 steps of a class per burst: SERVE_MAX_BURST, or fewer when every
 // active request needs fewer.  A request that reaches its step count stops
 // on the device (its control block turns inactive and its blocks exit at
@@ -243,7 +256,8 @@ struct Burst {
 // keeps SERVE_DEPTH bursts queued on its stream, so the GPU works on the
 // next burst while the host retires and admits requests.
 constexpr int SERVE_MAX_BURST = 8;
-constexpr int SERVE_DEPTH = 2;
+constexpr int SERVE_DEPTH = 2;       // default; ZA_SRV_DEPTH overrides (1 .. SERVE_DEPTH_MAX)
+constexpr int SERVE_DEPTH_MAX = 4;
 
 static int class_of(const za_problem& p) { return (p.dim == 2 ? 2 : 0) + (p.precision == ZA_FP32_RECON ? 1 : 0); }
 static int ncomp(const za_problem& p) { return p.dim == 1 ? 3 : 4; }
@@ -258,15 +272,16 @@ struct GraphKey {
 struct Class {
   hipStream_t stream = nullptr;
   BatchTable* dtab = nullptr;
-  BatchTable* htab[SERVE_DEPTH] = {};   // pinned: the table each queued burst uploaded
+  BatchTable* htab[SERVE_DEPTH_MAX] = {};   // pinned: the table each queued burst uploaded
   DevCtl* dctl = nullptr;               // MAX_SLOTS control blocks
-  DevCtl* hctl[SERVE_DEPTH] = {};       // pinned: control blocks after each queued burst
-  hipEvent_t ev[SERVE_DEPTH] = {};
+  DevCtl* hctl[SERVE_DEPTH_MAX] = {};       // pinned: control blocks after each queued burst
+  hipEvent_t ev[SERVE_DEPTH_MAX] = {};
   std::deque<Burst> inflight;           // oldest first
   std::vector<Req*> active;
   std::vector<int> free_slots;
   bool dirty = true;                    // the device table lags behind `active`
   std::map<GraphKey, hipGraphExec_t> graphs;
+  int64_t stat_bursts = 0, stat_steps = 0, stat_members = 0;   // ZA_SRV_STATS=1 prints them at destroy
 };
 
 }  // namespace zs
@@ -284,9 +299,15 @@ struct za_server {
   std::map<za_req_id, std::unique_ptr<Req>> reqs;
   hipStream_t xfer = nullptr;     // uploads and result downloads, beside the compute streams
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::thread th;
-  bool stop = false;
+  std::condition_variable cv_work, cv_done, cv_xfer;
+  std::thread th, xth;            // scheduler, transfers
+  bool stop = false, xstop = false;
+  std::deque<XJob> xjobs;         // transfers queued for xth
+  int64_t xpending = 0;           // transfers queued or running
+  std::vector<Req*> uploaded;     // uploads done, to be started by the scheduler
+  int admitting = 0;              // admitted requests not yet started
+  char* hpin = nullptr;           // pinned staging pool for uploads and results
+  Pool hpool;
   za_req_id next_id = 1;
   int64_t in_flight = 0;   // submitted and not finished
   std::string err;
@@ -295,6 +316,7 @@ struct za_server {
   int64_t fail_burst = 0, bursts = 0;
   bool graphs = true;   // replay a captured graph per class step (ZA_SRV_GRAPHS=0: direct launches)
   int64_t max_burst = SERVE_MAX_BURST;   // ZA_SRV_BURST overrides (1 .. 64)
+  int depth = SERVE_DEPTH;               // bursts queued per class
 };
 
 constexpr long long kServeMinWaves = 3072;   // 3 per SIMD of a 256-CU device
@@ -434,24 +456,39 @@ static void rebuild_table(const Class& C, BatchTable& h) {
   h.ytot = y;
 }
 
-// Mark r finished with status st (its result, if any, already in r->qout),
-// give back its pool space and control-block slot, and wake waiters.
-// Called with the lock held.
-static void finish_req(za_server* sv, Req* r, int st) {
-  if (r->done) return;
+// Bytes of one state of r in the pinned staging pool.
+static size_t host_bytes(const Req* r) { return (r->m * r->ncell * sizeof(double) + 255) & ~size_t(255); }
+
+// Take r out of its class (lock held): its slot is free and no later burst
+// table holds it; its pool memory stays until complete_req.
+static void retire_req(za_server* sv, Req* r) {
   Class& C = sv->cls[r->cls];
-  r->status = st;
-  if (r->bytes) sv->pool.release(r->off, r->bytes);
-  r->bytes = 0;
   if (r->slot >= 0) C.free_slots.push_back(r->slot);
   r->slot = -1;
-  r->done = true;
-  r->t_fin = now_ns();
-  sv->in_flight--;
   C.active.erase(std::remove(C.active.begin(), C.active.end(), r), C.active.end());
   for (Burst& b : C.inflight) b.members.erase(std::remove(b.members.begin(), b.members.end(), r), b.members.end());
   C.dirty = true;
+}
+
+// Mark r finished with status st (its result, if any, already in r->qout)
+// and release its pool memory (lock held).
+static void complete_req(za_server* sv, Req* r, int st) {
+  if (r->done) return;
+  r->status = st;
+  if (r->h_in) sv->hpool.release(r->h_in_off, host_bytes(r));
+  r->h_in = nullptr;
+  if (r->bytes) sv->pool.release(r->off, r->bytes);
+  r->bytes = 0;
+  r->done = true;
+  r->t_fin = now_ns();
+  sv->in_flight--;
   std::vector<double>().swap(r->q0);
+}
+
+static void finish_req(za_server* sv, Req* r, int st) {
+  if (r->done) return;
+  retire_req(sv, r);
+  complete_req(sv, r, st);
 }
 
 // A device failure in class c: drain its stream and end every request it
@@ -466,13 +503,11 @@ static void fail_class(za_server* sv, int c, const char* what) {
   sv->cv_done.notify_all();
 }
 
-// Admit waiting requests that fit (first fit in arrival order).  Pool space
-// and slots are taken under the lock; the initial states are uploaded with
-// the lock released, on the transfer stream (so an upload waits neither for
-// the queued bursts nor blocks submit and poll), and the control block and
-// the wave speeds of Q^0 are then enqueued on the class stream.
-static void admit(za_server* sv, std::unique_lock<std::mutex>& lk) {
-  int total = 0;
+// Admit waiting requests that fit (first fit in arrival order, lock held):
+// pool space and a slot are taken here, and the initial state is queued for
+// the transfer thread (activate_uploaded starts the request afterwards).
+static void admit(za_server* sv) {
+  int total = sv->admitting;   // admitted, upload not yet done
   for (int c = 0; c < NCLASS; ++c) total += (int)sv->cls[c].active.size();
   std::vector<Req*> picked;
   for (auto it = sv->waiting.begin(); it != sv->waiting.end();) {
@@ -514,19 +549,28 @@ static void admit(za_server* sv, std::unique_lock<std::mutex>& lk) {
     ++total;
     it = sv->waiting.erase(it);
   }
-  if (picked.empty()) return;
-  lk.unlock();
-  std::vector<int> ok(picked.size(), 1);
-  for (size_t k = 0; k < picked.size(); ++k) {
-    Req* r = picked[k];
-    ok[k] = hipMemcpyAsync(r->desc.st, r->q0.data(), r->m * r->ncell * sizeof(double), hipMemcpyHostToDevice,
-                           sv->xfer) == hipSuccess;
+  for (Req* r : picked) {
+    sv->xjobs.push_back({r, true});
+    ++sv->xpending;
+    ++sv->admitting;
   }
-  const bool up = hipStreamSynchronize(sv->xfer) == hipSuccess;
-  for (size_t k = 0; k < picked.size(); ++k) {
-    Req* r = picked[k];
-    if (!up || !ok[k]) continue;
+  if (!picked.empty()) sv->cv_xfer.notify_one();
+}
+
+// Requests whose upload finished (lock held): enqueue their control block
+// and the wave speeds of Q^0 on the class stream and make them active.
+static void activate_uploaded(za_server* sv) {
+  for (Req* r : sv->uploaded) {
     Class& C = sv->cls[r->cls];
+    --sv->admitting;
+    r->admitted = true;
+    r->t_adm = now_ns();
+    if (!r->xfer_ok) {
+      sv->err = "request upload failed";
+      finish_req(sv, r, ZA_ERR_DEVICE);
+      sv->cv_done.notify_all();
+      continue;
+    }
     const SlotDesc& d = r->desc;
     DevCtl v;
     std::memset(&v, 0, sizeof(v));
@@ -544,22 +588,80 @@ static void admit(za_server* sv, std::unique_lock<std::mutex>& lk) {
     else
       hipLaunchKernelGGL((k_wave_partial<SYS_EULER, 3>), dim3(d.stage_blocks), dim3(256), 0, C.stream, d.st,
                          r->ncell, d.ph, d.ctl, 0, d.part);
-    ok[k] = hipGetLastError() == hipSuccess;
-  }
-  lk.lock();
-  for (size_t k = 0; k < picked.size(); ++k) {
-    Req* r = picked[k];
-    Class& C = sv->cls[r->cls];
-    r->admitted = true;
-    r->t_adm = now_ns();
+    if (hipGetLastError() != hipSuccess) {
+      sv->err = "request start failed";
+      finish_req(sv, r, ZA_ERR_DEVICE);
+      sv->cv_done.notify_all();
+      continue;
+    }
     C.active.push_back(r);
     C.dirty = true;
-    if (!up || !ok[k]) {
-      sv->err = "request upload failed";
-      finish_req(sv, r, ZA_ERR_DEVICE);
-    } else {
-      std::vector<double>().swap(r->q0);
+    std::vector<double>().swap(r->q0);
+  }
+  sv->uploaded.clear();
+}
+
+// The transfer thread: uploads of admitted requests and downloads of
+// finished ones on the transfer stream, so that the scheduler keeps every
+// class's bursts queued meanwhile.  It takes every queued transfer at once,
+// issues the copies and waits once; copies between the device and the
+// pinned staging pool are plain DMA (the pageable fallback, when the pool is
+// full, is staged by the runtime).  An upload hands the request back to the
+// scheduler; a download completes it.
+static void xfer_worker(za_server* sv) {
+  (void)hipSetDevice(sv->device);
+  std::unique_lock<std::mutex> lk(sv->mu);
+  std::vector<XJob> batch;
+  while (true) {
+    sv->cv_xfer.wait(lk, [&] { return sv->xstop || !sv->xjobs.empty(); });
+    if (sv->xjobs.empty()) break;   // xstop and nothing left
+    batch.assign(sv->xjobs.begin(), sv->xjobs.end());
+    sv->xjobs.clear();
+    for (const XJob& j : batch) {   // pinned space for the results
+      Req* r = j.r;
+      size_t off;
+      if (!j.up && sv->hpool.alloc(host_bytes(r), &off)) {
+        r->h_out = (double*)(sv->hpin + off);
+        r->h_out_off = off;
+      }
     }
+    lk.unlock();
+    std::vector<char> ok(batch.size(), 1);
+    for (size_t k = 0; k < batch.size(); ++k) {
+      Req* r = batch[k].r;
+      const size_t n = r->m * r->ncell;
+      if (batch[k].up) {
+        const double* src = r->h_in ? r->h_in : r->q0.data();
+        ok[k] = hipMemcpyAsync(r->desc.st, src, n * sizeof(double), hipMemcpyHostToDevice, sv->xfer) == hipSuccess;
+      } else {
+        double* dst = r->h_out;
+        if (!dst) {
+          r->qout.reset(new double[n]);
+          dst = r->qout.get();
+        }
+        ok[k] = hipMemcpyAsync(dst, r->desc.st, n * sizeof(double), hipMemcpyDeviceToHost, sv->xfer) == hipSuccess;
+      }
+    }
+    const bool synced = hipStreamSynchronize(sv->xfer) == hipSuccess;
+    lk.lock();
+    bool any_up = false, any_down = false;
+    for (size_t k = 0; k < batch.size(); ++k) {
+      Req* r = batch[k].r;
+      --sv->xpending;
+      r->xfer_ok = synced && ok[k];
+      if (batch[k].up) {
+        if (r->h_in) sv->hpool.release(r->h_in_off, host_bytes(r));
+        r->h_in = nullptr;
+        sv->uploaded.push_back(r);
+        any_up = true;
+      } else {
+        if (!r->xfer_ok) sv->err = "result download failed";
+        complete_req(sv, r, r->xfer_ok ? r->status : (int)ZA_ERR_DEVICE);
+        any_down = true;
+      }
+    }
+    if (any_up) sv->cv_work.notify_one();
+    if (any_down) sv->cv_done.notify_all();
   }
 }
 
@@ -569,7 +671,7 @@ static void admit(za_server* sv, std::unique_lock<std::mutex>& lk) {
 static void launch_burst(za_server* sv, int c) {
   Class& C = sv->cls[c];
   int buf = 0;
-  if (!C.inflight.empty()) buf = 1 - C.inflight.back().buf;
+  if (!C.inflight.empty()) buf = (C.inflight.back().buf + 1) % sv->depth;   // fewer than depth in flight
   BatchTable& h = *C.htab[buf];
   rebuild_table(C, h);
   if (C.dirty) {
@@ -594,6 +696,9 @@ static void launch_burst(za_server* sv, int c) {
     }
   }
   for (Req* r : C.active) r->launched += burst;
+  C.stat_bursts++;
+  C.stat_steps += burst;
+  C.stat_members += (int64_t)C.active.size() * burst;
   if (hipMemcpyAsync(C.hctl[buf], C.dctl, MAX_SLOTS * sizeof(DevCtl), hipMemcpyDeviceToHost, C.stream) != hipSuccess ||
       hipEventRecord(C.ev[buf], C.stream) != hipSuccess) {
     fail_class(sv, c, "control block copy failed");
@@ -627,16 +732,17 @@ static void scheduler(za_server* sv) {
   std::unique_lock<std::mutex> lk(sv->mu);
   std::vector<Req*> fin;
   while (true) {
-    admit(sv, lk);
-    bool any = false;
+    admit(sv);
+    activate_uploaded(sv);
+    bool any = sv->xpending > 0;
     for (int c = 0; c < NCLASS; ++c) {
       Class& C = sv->cls[c];
-      if (!C.active.empty() && (int)C.inflight.size() < SERVE_DEPTH) launch_burst(sv, c);
+      if (!C.active.empty() && (int)C.inflight.size() < sv->depth) launch_burst(sv, c);
       any = any || !C.active.empty() || !C.inflight.empty();
     }
     if (!any) {
       if (sv->stop) break;
-      sv->cv_work.wait(lk, [&] { return sv->stop || !sv->waiting.empty(); });
+      sv->cv_work.wait(lk, [&] { return sv->stop || !sv->waiting.empty() || !sv->uploaded.empty(); });
       continue;
     }
     // completed bursts, oldest first per class
@@ -657,28 +763,19 @@ static void scheduler(za_server* sv) {
       }
     }
     if (!fin.empty()) {
-      // copy the results out with the lock released (the other classes'
-      // bursts keep running); a request leaves the device only afterwards
+      // out of their classes now; the transfer thread copies the results
+      // out and completes them (a request leaves the device only then)
       std::sort(fin.begin(), fin.end());
       fin.erase(std::unique(fin.begin(), fin.end()), fin.end());
-      lk.unlock();
-      std::vector<int> ok(fin.size(), 1);
-      for (size_t k = 0; k < fin.size(); ++k) {
-        Req* r = fin[k];
-        r->qout.resize(r->m * r->ncell);
-        ok[k] = hipMemcpyAsync(r->qout.data(), r->desc.st, r->m * r->ncell * sizeof(double),
-                               hipMemcpyDeviceToHost, sv->xfer) == hipSuccess;
+      for (Req* r : fin) {
+        retire_req(sv, r);
+        sv->xjobs.push_back({r, false});
+        ++sv->xpending;
       }
-      const bool down = hipStreamSynchronize(sv->xfer) == hipSuccess;
-      lk.lock();
-      for (size_t k = 0; k < fin.size(); ++k) {
-        if (!down || !ok[k]) sv->err = "result download failed";
-        finish_req(sv, fin[k], (!down || !ok[k]) ? (int)ZA_ERR_DEVICE : fin[k]->status);
-      }
-      sv->cv_done.notify_all();
+      sv->cv_xfer.notify_one();
     }
-    if (!progressed) {
-      // nothing finished yet: sleep briefly (a submission wakes us)
+    if (!progressed && sv->uploaded.empty()) {
+      // nothing finished yet: sleep briefly (a submission or an upload wakes us)
       sv->cv_work.wait_for(lk, std::chrono::microseconds(50));
     }
   }
@@ -701,11 +798,19 @@ za_status za_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t d
   if (const char* e = std::getenv("ZA_SRV_FAIL_BURST")) sv->fail_burst = std::atoll(e);
   if (const char* e = std::getenv("ZA_SRV_GRAPHS")) sv->graphs = std::atoi(e) != 0;
   if (const char* e = std::getenv("ZA_SRV_BURST")) sv->max_burst = std::max(1, std::min(std::atoi(e), 64));
+  if (const char* e = std::getenv("ZA_SRV_DEPTH")) sv->depth = std::max(1, std::min(std::atoi(e), SERVE_DEPTH_MAX));
   if (hipSetDevice(device) != hipSuccess) return fail(ZA_ERR_DEVICE);
   void* p = nullptr;
   if (hipMalloc(&p, hbm_budget_bytes) != hipSuccess) return fail(ZA_ERR_NOMEM);
   sv->pool_base = (char*)p;
   sv->pool.init(hbm_budget_bytes);
+  {
+    // pinned staging: as large as the device budget, at most 1 GiB
+    const size_t hb = std::min<size_t>(hbm_budget_bytes, size_t(1) << 30);
+    if (hipHostMalloc(&p, hb, hipHostMallocDefault) != hipSuccess) return fail(ZA_ERR_NOMEM);
+    sv->hpin = (char*)p;
+    sv->hpool.init(hb);
+  }
   // non-blocking streams: nothing here waits on the null stream
   if (hipStreamCreateWithFlags(&sv->xfer, hipStreamNonBlocking) != hipSuccess) return fail(ZA_ERR_DEVICE);
   for (int c = 0; c < NCLASS; ++c) {
@@ -715,7 +820,7 @@ za_status za_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t d
     C.dtab = (BatchTable*)p;
     if (hipMalloc(&p, MAX_SLOTS * sizeof(DevCtl)) != hipSuccess) return fail(ZA_ERR_NOMEM);
     C.dctl = (DevCtl*)p;
-    for (int b = 0; b < SERVE_DEPTH; ++b) {
+    for (int b = 0; b < SERVE_DEPTH_MAX; ++b) {
       if (hipHostMalloc(&p, sizeof(BatchTable), hipHostMallocDefault) != hipSuccess) return fail(ZA_ERR_NOMEM);
       C.htab[b] = (BatchTable*)p;
       std::memset(C.htab[b], 0, sizeof(BatchTable));
@@ -728,6 +833,7 @@ za_status za_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t d
     if (hipMemcpy(C.dtab, C.htab[0], sizeof(BatchTable), hipMemcpyHostToDevice) != hipSuccess) return fail(ZA_ERR_DEVICE);
   }
   za_server* raw = sv.release();
+  raw->xth = std::thread(xfer_worker, raw);
   raw->th = std::thread(scheduler, raw);
   *out = raw;
   return ZA_OK;
@@ -750,12 +856,25 @@ za_status za_server_submit(za_server* sv, const za_problem* p, const double* q0,
   r->cls = class_of(*p);
   r->m = ncomp(*p);
   r->ncell = (size_t)p->nx * p->ny;
-  r->q0.assign(q0, q0 + r->m * r->ncell);
   r->n_steps = n_steps;
+  {
+    size_t off;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->hpool.alloc(host_bytes(r.get()), &off)) {
+      r->h_in = (double*)(sv->hpin + off);
+      r->h_in_off = off;
+    }
+  }
+  // the copy runs with the lock released; the request is not queued yet
+  if (r->h_in) std::memcpy(r->h_in, q0, r->m * r->ncell * sizeof(double));
+  else r->q0.assign(q0, q0 + r->m * r->ncell);
   r->t_arr = now_ns();
   {
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (sv->stop) return ZA_ERR_ARG;
+    if (sv->stop) {
+      if (r->h_in) sv->hpool.release(r->h_in_off, host_bytes(r.get()));
+      return ZA_ERR_ARG;
+    }
     r->id = sv->next_id++;
     *id = r->id;
     sv->waiting.push_back(r.get());
@@ -768,26 +887,34 @@ za_status za_server_submit(za_server* sv, const za_problem* p, const double* q0,
 
 za_status za_server_poll(za_server* sv, za_req_id id, int32_t* done, double* q_out, za_req_stats* st) {
   if (!sv || !done) return ZA_ERR_ARG;
-  std::lock_guard<std::mutex> lk(sv->mu);
-  auto it = sv->reqs.find(id);
-  if (it == sv->reqs.end()) return ZA_ERR_ARG;
-  Req* r = it->second.get();
-  *done = r->done ? 1 : 0;
-  if (st) {
-    st->arrival_ns = r->t_arr;
-    st->admit_ns = r->t_adm;
-    st->finish_ns = r->t_fin;
-    st->steps = r->steps;
-    st->interfaces = r->interfaces;
-    st->status = r->status;
-  }
-  if (r->done && q_out) {
-    std::memcpy(q_out, r->qout.data(), r->qout.size() * sizeof(double));
-    const za_status s = (za_status)r->status;
+  std::unique_ptr<Req> own;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(id);
+    if (it == sv->reqs.end()) return ZA_ERR_ARG;
+    Req* r = it->second.get();
+    *done = r->done ? 1 : 0;
+    if (st) {
+      st->arrival_ns = r->t_arr;
+      st->admit_ns = r->t_adm;
+      st->finish_ns = r->t_fin;
+      st->steps = r->steps;
+      st->interfaces = r->interfaces;
+      st->status = r->status;
+    }
+    if (!(r->done && q_out)) return r->done ? (za_status)r->status : ZA_OK;
+    own = std::move(it->second);   // the result is copied with the lock released
     sv->reqs.erase(it);
-    return s;
   }
-  return r->done ? (za_status)r->status : ZA_OK;
+  const size_t n = own->m * own->ncell;
+  if (own->h_out) {
+    std::memcpy(q_out, own->h_out, n * sizeof(double));
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->hpool.release(own->h_out_off, host_bytes(own.get()));
+  } else if (own->qout) {
+    std::memcpy(q_out, own->qout.get(), n * sizeof(double));
+  }
+  return (za_status)own->status;
 }
 
 za_status za_server_drain(za_server* sv) {
@@ -806,13 +933,29 @@ za_status za_server_destroy(za_server* sv) {
   }
   sv->cv_work.notify_all();
   if (sv->th.joinable()) sv->th.join();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->xstop = true;
+  }
+  sv->cv_xfer.notify_all();
+  if (sv->xth.joinable()) sv->xth.join();
+  if (const char* e = std::getenv("ZA_SRV_STATS")) {
+    if (std::atoi(e) != 0) {
+      for (int c = 0; c < NCLASS; ++c) {
+        const Class& C = sv->cls[c];
+        std::fprintf(stderr, "za_server class %d: %lld bursts, %.2f steps per burst, %.2f requests per step\n", c,
+                     (long long)C.stat_bursts, C.stat_bursts ? (double)C.stat_steps / C.stat_bursts : 0.0,
+                     C.stat_steps ? (double)C.stat_members / C.stat_steps : 0.0);
+      }
+    }
+  }
   for (int c = 0; c < NCLASS; ++c) {
     Class& C = sv->cls[c];
     if (C.stream) (void)hipStreamSynchronize(C.stream);
     for (auto& kv : C.graphs) (void)hipGraphExecDestroy(kv.second);
     if (C.dtab) (void)hipFree(C.dtab);
     if (C.dctl) (void)hipFree(C.dctl);
-    for (int b = 0; b < SERVE_DEPTH; ++b) {
+    for (int b = 0; b < SERVE_DEPTH_MAX; ++b) {
       if (C.htab[b]) (void)hipHostFree(C.htab[b]);
       if (C.hctl[b]) (void)hipHostFree(C.hctl[b]);
       if (C.ev[b]) (void)hipEventDestroy(C.ev[b]);
@@ -824,6 +967,7 @@ za_status za_server_destroy(za_server* sv) {
     (void)hipStreamDestroy(sv->xfer);
   }
   if (sv->pool_base) (void)hipFree(sv->pool_base);
+  if (sv->hpin) (void)hipHostFree(sv->hpin);
   delete sv;
   return ZA_OK;
 }
