@@ -533,25 +533,26 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
 #pragma unroll
         for (int c = 0; c < M; ++c) qb[c] = 0.0;
       }
+      // ca Q^n + cb Q - cb dt (F_{i+1/2} - F_{i-1/2}) / dx, the same
+      // operations as the looped sweep
+      const double kx = -(a.cb * sk.dt) * a.g.inv_dx;
 #pragma unroll
-      for (int c = 0; c < M; ++c) {
-        const double L = -(fl[wv][c][lane + 1] - fl[wv][c][lane]) * a.g.inv_dx;
-        a.out[c * cs + idx] = fma(a.ca, qb[c], a.cb * fma(sk.dt, L, qc[c]));
-      }
+      for (int c = 0; c < M; ++c)
+        a.out[c * cs + idx] = fma(a.ca, qb[c], fma(kx, fl[wv][c][lane + 1] - fl[wv][c][lane], a.cb * qc[c]));
     } else {
       double qnew[M], q0[M], qs[M];
       if (MODE == MODE_STAGE) {   // loads first (see the y-sweep epilogue)
 #pragma unroll
         for (int c = 0; c < M; ++c) { q0[c] = a.qn[c * cs + idx]; qs[c] = a.q[c * cs + idx]; }
       }
+      const double kx = -(a.cb * sk.dt) * a.g.inv_dx;
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        const double L = -(fl[wv][c][lane + 1] - fl[wv][c][lane]) * a.g.inv_dx;
         const size_t o = c * cs + idx;
         if (MODE == MODE_RHS) {
-          a.out[o] = L;
+          a.out[o] = -(fl[wv][c][lane + 1] - fl[wv][c][lane]) * a.g.inv_dx;
         } else {  // MODE_STAGE (1D)
-          qnew[c] = fma(a.ca, q0[c], a.cb * fma(sk.dt, L, qs[c]));
+          qnew[c] = fma(a.ca, q0[c], fma(kx, fl[wv][c][lane + 1] - fl[wv][c][lane], a.cb * qs[c]));
           a.out[o] = qnew[c];
         }
       }
@@ -644,6 +645,8 @@ __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<d
   double* const ring = &xr[wv][0];
   double(*const fw)[66] = fl[wv];
   const int bcx = a.g.bc_x;
+  // ca Q^n + cb Q - cb dt (F_{i+1/2} - F_{i-1/2}) / dx
+  const double kx = -(a.cb * sk.dt) * a.g.inv_dx;
   // ring slot of cell k is (k - s0 + R) mod 128; cells s0 - R .. s0 - R + 63 first
   double rs[NPART];
 #pragma unroll
@@ -702,8 +705,7 @@ __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<d
           qc = ring[si];
         }
         const double Fm = lane == 0 ? fw[c][65] : fw[c][lane];
-        const double L = -(fw[c][lane + 1] - Fm) * a.g.inv_dx;
-        qnew[c] = fma(a.ca, qb[c], a.cb * fma(sk.dt, L, qc));
+        qnew[c] = fma(a.ca, qb[c], fma(kx, fw[c][lane + 1] - Fm, a.cb * qc));
         *d = qnew[c];
         d += dstride;
       }
@@ -806,7 +808,7 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
   int sb = g * RS;
   int fk = g + 1, fkm = g;
   constexpr int RING_RS = YS_RING * RS;
-  const double cbdt = a.cb * sk.dt;
+  const double ky = -(a.cb * sk.dt) * a.g.inv_dy;
   const int nst = (kend - y0) / YS_ROWS + 1;
   for (int st = 0; st < nst; ++st) {
     progress_prio(st, nst);
@@ -878,12 +880,12 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
       }
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        const double L = -(fw[fk][c][cl] - fw[fkm][c][cl]) * a.g.inv_dy;
+        const double dF = fw[fk][c][cl] - fw[fkm][c][cl];
         const size_t o = c * cs + idx;
         if (MODE == MODE_RHS) {
-          a.out[o] = lx[c] + L;
-        } else {  // MODE_STAGE: the x-sweep left ca Q^n + cb (Q + dt L_x)
-          qnew[c] = fma(cbdt, L, lx[c]);
+          a.out[o] = lx[c] - dF * a.g.inv_dy;
+        } else {  // MODE_STAGE: the x-sweep left ca Q^n + cb Q - cb dt dF_x / dx
+          qnew[c] = fma(ky, dF, lx[c]);
           a.out[o] = qnew[c];
         }
       }
