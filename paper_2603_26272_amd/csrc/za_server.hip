@@ -806,10 +806,22 @@ za_status za_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t d
   sv->pool.init(hbm_budget_bytes);
   {
     // pinned staging: as large as the device budget, at most 1 GiB
-    const size_t hb = std::min<size_t>(hbm_budget_bytes, size_t(1) << 30);
-    if (hipHostMalloc(&p, hb, hipHostMallocDefault) != hipSuccess) return fail(ZA_ERR_NOMEM);
-    sv->hpin = (char*)p;
-    sv->hpool.init(hb);
+    // (ZA_SRV_PINNED_MB overrides; 0: none).  If the host cannot pin that
+    // much, halve it down to 16 MiB, else run without: requests that find no
+    // pinned space pass through pageable memory.
+    size_t hb = std::min<size_t>(hbm_budget_bytes, size_t(1) << 30);
+    if (const char* e = std::getenv("ZA_SRV_PINNED_MB")) hb = (size_t)std::max(0LL, std::atoll(e)) << 20;
+    while (hb >= (size_t(16) << 20) && hipHostMalloc(&p, hb, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      hb /= 2;
+    }
+    if (hb >= (size_t(16) << 20) || (hb > 0 && hipHostMalloc(&p, hb, hipHostMallocDefault) == hipSuccess)) {
+      sv->hpin = (char*)p;
+      sv->hpool.init(hb);
+    } else {
+      (void)hipGetLastError();
+      sv->hpool.init(0);
+    }
   }
   // non-blocking streams: nothing here waits on the null stream
   if (hipStreamCreateWithFlags(&sv->xfer, hipStreamNonBlocking) != hipSuccess) return fail(ZA_ERR_DEVICE);

@@ -60,6 +60,21 @@ def test_served_equals_single_context(dev):
         assert np.array_equal(q, ref), (P.dim, P.precision, np.abs(q - ref).max())
 
 
+@pytest.mark.parametrize("pinned_mb", ["0", "1"])
+def test_pageable_staging_bitwise(dev, monkeypatch, pinned_mb):
+    """Uploads and result downloads through pageable memory (no pinned
+    staging pool, or one too small for most requests) give the same states
+    as the pinned path."""
+    reqs = [(r.problem, r.q0, min(r.steps, 40)) for r in
+            W.serving_stream(200.0, n_requests=12, seed=5, max_1d=8192, max_2d=256)]
+    pinned = serve(reqs, budget=2 << 30, slots=12)
+    monkeypatch.setenv("ZA_SRV_PINNED_MB", pinned_mb)
+    pageable = serve(reqs, budget=2 << 30, slots=12)
+    for i, (a, b) in enumerate(zip(pinned, pageable)):
+        assert a[0] == b[0] == 0
+        assert np.array_equal(a[1], b[1]), i
+
+
 def test_served_matches_oracle(dev):
     P, q0 = W.riemann_1d(7, 512)
     (st, q, _), = serve([(P, q0, 30)])
