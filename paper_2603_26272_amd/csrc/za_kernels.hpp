@@ -62,6 +62,14 @@ __device__ __forceinline__ int bc_map(int j, int n, int bc) {
   return j < 0 ? 0 : (j >= n ? n - 1 : j);
 }
 
+// bc_map for a wavefront whose cells lie in [j0, j0 + span) with j0
+// wave-uniform: away from the boundary (the usual case) a uniform branch
+// skips the ghost rule and its integer arithmetic.
+__device__ __forceinline__ int bc_map_span(int j, int j0, int span, int n, int bc) {
+  if (j0 >= 0 && j0 + span <= n) return j;
+  return bc_map(j, n, bc);
+}
+
 // ---------------------------------------------------------------------------
 // Scalar flux functions and their derivatives (Section 2; Section 4.1).
 // ---------------------------------------------------------------------------
@@ -478,7 +486,8 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
     for (int t = 0; t < NX; ++t) {
       const int idx = lane + 64 * t;
       if (idx < XS_CELLS + 2 * R)
-        cell_load<SYS, M, 0>(a.q + row, cs, (size_t)bc_map(c0 - R + idx, nx, a.g.bc_x), qx[t]);
+        cell_load<SYS, M, 0>(a.q + row, cs, (size_t)bc_map_span(c0 - R + idx, c0 - R + 64 * t, 64, nx, a.g.bc_x),
+                             qx[t]);
     }
 #pragma unroll
     for (int t = 0; t < NX; ++t) {
@@ -662,7 +671,7 @@ __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<d
   for (int j = 0; j < nch; ++j) {
     const int I0 = s0 + 64 * j;
     wave_sync();   // the records of cells I0 - R .. I0 + 124 - R are in the ring
-    if (j + 1 < nch) xl_load<SYS, M>(rowq, cs, bc_map(I0 + 128 - R + lane, nx, bcx), qp);
+    if (j + 1 < nch) xl_load<SYS, M>(rowq, cs, bc_map_span(I0 + 128 - R + lane, I0 + 128 - R, 64, nx, bcx), qp);
     // the cell this lane completes, and its Q^n (fetched before the fluxes)
     const int i = I0 - 1 + lane;
     const bool upd = (j > 0 || lane > 0) && i < nx;
@@ -820,7 +829,7 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
     const bool need = rn <= kend + R - 1 && xin;
     double qp[M];
     if (need) {
-      const size_t off = (size_t)bc_map(rn, ny, a.g.bc_y) * nx;
+      const size_t off = (size_t)bc_map_span(rn, k0 + YS_ROWS + R - 1, YS_ROWS, ny, a.g.bc_y) * nx;
 #pragma unroll
       for (int c = 0; c < M; ++c) qp[c] = a.q[off + xc + c * cs];
     }
