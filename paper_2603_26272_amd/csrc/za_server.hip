@@ -314,6 +314,8 @@ struct za_server {
   // host-side fault injection for tests of the failure path
   // (ZA_SRV_FAIL_BURST=k: the k-th burst launch reports a launch error)
   int64_t fail_burst = 0, bursts = 0;
+  // (ZA_SRV_FAIL_XFER=k: the k-th upload or download reports a copy error)
+  int64_t fail_xfer = 0, xfers = 0;
   bool graphs = true;   // replay a captured graph per class step (ZA_SRV_GRAPHS=0: direct launches)
   int64_t max_burst = SERVE_MAX_BURST;   // ZA_SRV_BURST overrides (1 .. 64)
   int depth = SERVE_DEPTH;               // bursts queued per class
@@ -630,6 +632,10 @@ static void xfer_worker(za_server* sv) {
     for (size_t k = 0; k < batch.size(); ++k) {
       Req* r = batch[k].r;
       const size_t n = r->m * r->ncell;
+      if (sv->fail_xfer > 0 && ++sv->xfers == sv->fail_xfer) {
+        ok[k] = 0;   // injected: this transfer reports a failure, no copy is made
+        continue;
+      }
       if (batch[k].up) {
         const double* src = r->h_in ? r->h_in : r->q0.data();
         ok[k] = hipMemcpyAsync(r->desc.st, src, n * sizeof(double), hipMemcpyHostToDevice, sv->xfer) == hipSuccess;
@@ -796,6 +802,7 @@ za_status za_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t d
   sv->max_slots = max_slots;
   sv->device = device;
   if (const char* e = std::getenv("ZA_SRV_FAIL_BURST")) sv->fail_burst = std::atoll(e);
+  if (const char* e = std::getenv("ZA_SRV_FAIL_XFER")) sv->fail_xfer = std::atoll(e);
   if (const char* e = std::getenv("ZA_SRV_GRAPHS")) sv->graphs = std::atoi(e) != 0;
   if (const char* e = std::getenv("ZA_SRV_BURST")) sv->max_burst = std::max(1, std::min(std::atoi(e), 64));
   if (const char* e = std::getenv("ZA_SRV_DEPTH")) sv->depth = std::max(1, std::min(std::atoi(e), SERVE_DEPTH_MAX));

@@ -186,3 +186,38 @@ def test_injected_launch_failure_ends_requests_without_hang(dev, monkeypatch):
     assert all(s in (0, za.ZA_ERR_DEVICE) for s in statuses)
     res = serve(reqs[:2])
     assert all(r[0] == 0 for r in res)
+
+
+@pytest.mark.parametrize("which", ["upload", "download"])
+def test_injected_transfer_failure_ends_one_request(dev, monkeypatch, which):
+    """A failed copy (injected on the host: ZA_SRV_FAIL_XFER=k makes the
+    transfer thread's k-th copy report an error without copying) ends that
+    one request with ZA_ERR_DEVICE; the others finish normally, drain returns
+    (reporting the error) and a new server is unaffected.  Requests are
+    submitted one by one after the previous finished, so copy 1 is the first
+    upload and copy 4 the second download."""
+    from paper_2603_26272_amd import za
+    monkeypatch.setenv("ZA_SRV_FAIL_XFER", "1" if which == "upload" else "4")
+    reqs = [(*W.riemann_1d(60 + s, 700), 9) for s in range(3)]
+    statuses = []
+    with za.Server(1 << 30, 8) as sv:
+        monkeypatch.delenv("ZA_SRV_FAIL_XFER")
+        ids = []
+        for P, q0, n in reqs:
+            ids.append(sv.submit(P, q0, n))
+            try:
+                sv.drain()
+            except za.ZaError as e:
+                assert e.status == za.ZA_ERR_DEVICE
+        for rid, (P, q0, n) in zip(ids, reqs):
+            done, st, q, stats = sv.poll(rid, P)
+            assert done
+            statuses.append(st)
+            if st == 0:
+                assert np.array_equal(q, ctx_solve(P, q0, n, dev))
+    bad = 0 if which == "upload" else 1
+    assert statuses[bad] == za.ZA_ERR_DEVICE
+    assert all(s == 0 for i, s in enumerate(statuses) if i != bad), statuses
+    res = serve(reqs[:2])
+    assert all(r[0] == 0 for r in res)
+
