@@ -23,6 +23,7 @@ namespace za {
 template <class T>
 struct WeightCfg {
   T eps16;    // 16 epsilon   (Z weights, indicators of 2v scaled by 4)
+  T eps6;     // 6 epsilon    (FP64 Z weights from differences, za6_diff)
   T eps4;     // 4 epsilon    (Ai weights after dividing by mu(2v)^2;
               //               order-2r Z weights on 2v)
   T eps1;     // epsilon      (order-2r Ai weights after dividing by mu(2v)^2)
@@ -134,17 +135,9 @@ __device__ __forceinline__ T z_alpha(T tau, T b, T bmin, const WeightCfg<T>& w) 
 // T/(B + 16 eps) with identical rounding.  (Ai: mu(s) = 2 mu(f) with 2 mu_0,
 // then T/mu(s)^2 and B/mu(s)^2 are 4 tau/mu^2 and 4 beta/mu^2, so 4 eps.)
 //
-// FP64 fast path: the weights are evaluated over a common denominator,
-//   2f = sum_k d_k (b_k + T) P_k q_k / sum_k d_k (b_k + T) P_k,
-//   b_k = B_k + 16 eps, P_k = prod_{j != k} b_j  (the 1/20 cancels),
-//   (b_k + T) P_k = P + T P_k with P = prod_j b_j,
-// algebraically identical to the normalised weights with one division
-// instead of five.  These kernels run for 1e-70 <= eps <= 1e-40, so
-// b_k >= 1.6e-69 keeps every product above 6e-276 and nothing underflows
-// (a smaller eps takes the general kernels); the products overflow only for flux values beyond
-// about 1e37, and the resulting non-finite state is reported.  FP32 keeps the
-// direct form (three indicators at 16 eps_32 would underflow) with the
-// hardware reciprocal.
+// This direct form serves FP32 (three indicators at 16 eps_32 would
+// underflow in a product of weights) and the general weights; the FP64 Z
+// weights take za6_diff below.
 // ---------------------------------------------------------------------------
 template <class T, int WV>
 __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const WeightCfg<T>& w) {
@@ -168,24 +161,6 @@ __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const Weigh
   const T k133 = T(13) / T(3);
   const T t5 = (e3 - e0) + T(3) * (e1 - e2);   // fifth difference
   const T t2 = t5 + t5;
-  if (WV == WV_Z1 && sizeof(T) == sizeof(double)) {
-    // b_k = B_k + 16 eps with the epsilon folded into the sum of squares;
-    // the mean of the four b's then carries it too
-    const T b0 = fma(k133 * e0, e0, fma(g0, g0, w.eps16));
-    const T b1 = fma(k133 * e1, e1, fma(g1, g1, w.eps16));
-    const T b2 = fma(k133 * e2, e2, fma(g2, g2, w.eps16));
-    const T bd = fma(k133 * e3, e3, fma(g3, g3, w.eps16));
-    const T b3 = T(0.25) * ((b0 + b1) + (b2 + bd));
-    const T tau = t2 * t2;
-    // (b_k + T) P_k = P + T P_k with P = b0 b1 b2 b3
-    const T p01 = b0 * b1, p23 = b2 * b3;
-    const T P = p01 * p23;
-    const T w0 = fma(tau, b1 * p23, P);
-    const T v1 = fma(tau, b0 * p23, P);   // w_1 / 9
-    const T v2 = fma(tau, p01 * b3, P);   // w_2 / 9
-    const T w3 = fma(tau, p01 * b2, P);
-    return div_nr(fma(w0, q0, fma(T(9), fma(v1, q1, v2 * q2), w3 * q3)), fma(T(9), v1 + v2, w0 + w3));
-  }
   T B0 = fma(k133 * e0, e0, g0 * g0);
   T B1 = fma(k133 * e1, e1, g1 * g1);
   T B2 = fma(k133 * e2, e2, g2 * g2);
@@ -212,6 +187,106 @@ __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const Weigh
   const T a0 = z_alpha<T, WV>(tau, b0, bmin, w), a1 = T(9) * z_alpha<T, WV>(tau, b1, bmin, w),
           a2 = T(9) * z_alpha<T, WV>(tau, b2, bmin, w), a3 = z_alpha<T, WV>(tau, b3, bmin, w);
   return div_nr(fma(a0, q0, fma(a1, q1, fma(a2, q2, a3 * q3))), (a0 + a1) + (a2 + a3));
+}
+
+// ---------------------------------------------------------------------------
+// FP64 WENO-ZA6 with the paper's Z weights (p = 1, L = q = 1), evaluated from
+// the first differences d_j = s_{j+1} - s_j (j = 0..4) of s = 2 (f_{i-2}, ..,
+// f_{i+3}) and measured from the anchor value s_A (A = 2 or 3): returns
+// 6 (R - s_A), R twice the reconstructed flux as in za6.  Since the weights
+// sum to one, R - s_A = sum_k omega_k (q_k - s_A), and 6 (q_k - s_A) has small
+// integer coefficients in the d's:
+//   A = 2:  5 d1 - 2 d0,  d1 + 2 d2,  4 d2 - d3,  6 d2 - 5 d3 + 2 d4
+//   A = 3:  5 d1 - 2 d0 - 6 d2,  d1 - 4 d2,  -2 d2 - d3,  2 d4 - 5 d3
+// (eq:subflux_S6_coeffs written around s_A).
+//
+// Indicators.  With e and g the second differences and twice the slopes of
+// za6, 6 beta_k(f) = (3/8) ((13/3) e_k^2 + g_k^2) (eq:SI_S6 with s = 2f) is a
+// positive definite quadratic form in the two differences (u, w) = (d_k,
+// d_{k+1}) of its stencil, 5 w^2 - 5.5 u w + 2 u^2 (k = 0), 2 w^2 - 2.5 u w +
+// 2 u^2 (k = 1), 2 w^2 - 5.5 u w + 5 u^2 (k = 2) and 5 w^2 - 14.5 u w + 11 u^2
+// (downwind candidate on I_i), and each is written as a sum of two squares
+// of one-FMA linear forms, x^2 + y^2:
+//   k = 0:  x, y = kA0 w - u, kC0 w - u             kA0, kC0 = (11 +- sqrt 39)/8
+//   k = 1:  x, y = kA1 w - u, kC1 w - u             kA1, kC1 = (5 +- sqrt 39)/8
+//   k = 2:  x, y = kA0 u - w, kC0 u - w             (k = 0 mirrored)
+//   k = 3:  x, y = kA3 u - w, kC3 u - 2 w           kA3 = 1.45 + sqrt(39)/10,
+//                                                   kC3 = 2.9 - sqrt(39)/20
+// (matching the coefficients: kA + kC and kA^2 + kC^2 give the cross and
+// square terms; 2 d4 is shared with the candidates).  Likewise
+// 6 tau = 1.5 t5^2 with t5 = d0 - 4 d1 + 6 d2 - 4 d3 + d4 the fifth
+// difference of s (eq:GSI).  Scaling every indicator, tau and eps by the
+// same factor leaves the weights unchanged.
+//
+// Weights over a common denominator,
+//   R - s_A = sum_k d_k (b_k + T) P_k (q_k - s_A) / sum_k d_k (b_k + T) P_k,
+//   b_k = 6 (beta_k + eps), T = 6 tau, P_k = prod_{j != k} b_j
+//   (the 1/20 of d cancels), (b_k + T) P_k = P + T P_k with P = prod_j b_j,
+// algebraically identical to the normalised weights of eq:weights_unnormalized
+// with one division instead of five.  These kernels run for
+// 1e-70 <= eps <= 1e-40, so b_k >= 6e-70 keeps every product above 1e-276
+// and nothing underflows (a smaller eps takes the general kernels); the
+// products overflow only for flux values beyond about 1e37, and the
+// resulting non-finite state is reported.
+// ---------------------------------------------------------------------------
+template <int A>
+__device__ __forceinline__ double za6_diff(const double (&d)[5], const WeightCfg<double>& w) {
+  static_assert(A == 2 || A == 3, "anchor s_2 or s_3");
+  const double d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
+  const double d4x2 = d4 + d4;
+  const double kA0 = 2.1556247497997997757, kC0 = 0.59437525020020022427;   // (11 +- sqrt 39)/8
+  const double kA1 = 1.4056247497997997757, kC1 = -0.15562474979979977573;  // (5 +- sqrt 39)/8
+  const double kA3 = 2.0744997998398398206;   // 1.45 + sqrt(39)/10
+  const double kC3 = 2.5877501000800800897;   // 2.9 - sqrt(39)/20
+  const double x0 = fma(kA0, d1, -d0), y0 = fma(kC0, d1, -d0);
+  const double x1 = fma(kA1, d2, -d1), y1 = fma(kC1, d2, -d1);
+  const double x2 = fma(kA0, d2, -d3), y2 = fma(kC0, d2, -d3);
+  const double x3 = fma(kA3, d3, -d4), y3 = fma(kC3, d3, -d4x2);
+  const double b0 = fma(x0, x0, fma(y0, y0, w.eps6));
+  const double b1 = fma(x1, x1, fma(y1, y1, w.eps6));
+  const double b2 = fma(x2, x2, fma(y2, y2, w.eps6));
+  const double bd = fma(x3, x3, fma(y3, y3, w.eps6));
+  const double b3 = 0.25 * ((b0 + b1) + (b2 + bd));   // eq:SI_downwind
+  const double t5 = fma(6.0, d2, fma(-4.0, d1 + d3, d0 + d4));
+  const double tau = (1.5 * t5) * t5;
+  const double p01 = b0 * b1, p23 = b2 * b3;
+  const double P = p01 * p23;
+  const double w0 = fma(tau, b1 * p23, P);
+  const double v1 = fma(tau, b0 * p23, P);   // w_1 / 9
+  const double v2 = fma(tau, p01 * b3, P);   // w_2 / 9
+  const double w3 = fma(tau, p01 * b2, P);
+  // the candidates last: fewer values live across the weights
+  double t0, t1, t2, t3;
+  if (A == 2) {
+    t0 = fma(5.0, d1, -(d0 + d0));
+    t1 = fma(2.0, d2, d1);
+    t2 = fma(4.0, d2, -d3);
+    t3 = fma(6.0, d2, fma(-5.0, d3, d4x2));
+  } else {
+    t0 = fma(-6.0, d2, fma(5.0, d1, -(d0 + d0)));
+    t1 = fma(-4.0, d2, d1);
+    t2 = fma(-2.0, d2, -d3);
+    t3 = fma(-5.0, d3, d4x2);
+  }
+  return div_nr(fma(w0, t0, fma(9.0, fma(v1, t1, v2 * t2), w3 * t3)), fma(9.0, v1 + v2, w0 + w3));
+}
+
+// Both Lax-Friedrichs halves of one characteristic field (eq:LF) from the
+// differences dw, dg of its state and flux values between neighbouring
+// stencil points and its flux value g_2 at x_i: s^{+-} = g +- a w, and the
+// negative half takes its six values in reverse order, whose differences
+// are -(dg - a dw) reversed.  Anchoring the positive half at s^+_2 and the
+// reversed negative half at its fourth value s^-_2 gives
+// F = (R^+ + R^-)/2 = g_2 + (6 (R^+ - s^+_2) + 6 (R^- - s^-_2)) / 12.
+__device__ __forceinline__ double split_diff(const double (&dw)[5], const double (&dg)[5], double g2, double a,
+                                             const WeightCfg<double>& cfg) {
+  double dp[5], dm[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    dp[k] = fma(a, dw[k], dg[k]);
+    dm[4 - k] = fma(a, dw[k], -dg[k]);
+  }
+  return fma(1.0 / 12.0, za6_diff<2>(dp, cfg) + za6_diff<3>(dm, cfg), g2);
 }
 
 // ---------------------------------------------------------------------------
@@ -306,6 +381,15 @@ __device__ __forceinline__ T zar(const T (&s)[2 * R], const WeightCfg<T>& w) {
 // the reconstruction.
 template <class T, int WV, int R = 3>
 __device__ __forceinline__ T split_pair(const T (&w)[2 * R], const T (&g)[2 * R], T a, const WeightCfg<T>& cfg) {
+  if constexpr (R == 3 && WV == WV_Z1 && sizeof(T) == sizeof(double)) {
+    double dw[5], dg[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      dw[k] = w[k + 1] - w[k];
+      dg[k] = g[k + 1] - g[k];
+    }
+    return split_diff(dw, dg, g[2], a, cfg);
+  }
   T p[2 * R], m[2 * R];
 #pragma unroll
   for (int j = 0; j < 2 * R; ++j) {
@@ -396,6 +480,22 @@ __device__ __forceinline__ void roe_side(const T* __restrict__ rec, int fs, int 
   hs = (E + p) * r;
 }
 
+// Projection onto the characteristic fields with the left eigenvectors at the
+// Roe state (factored as in euler_flux, acoustic rows scaled by 2c): of a
+// state (Q0, Q1, Q2, E) or, with (Q1, F1, F2, F3) in their places, of a
+// physical flux.  Linear, so it also projects differences.
+template <class T, int M>
+__device__ __forceinline__ void char_project(T u, T v, T q2, T k1, T b1, T Q0, T Q1, T Q2, T E, T (&W)[M]) {
+  T K = fma(u, Q1, -E);
+  if constexpr (M == 4) K = fma(v, Q2, K);
+  const T P = fma(q2, Q0, -K);
+  const T D = fma(u, Q0, -Q1);
+  W[0] = fma(k1, P, D);
+  W[1] = fma(-b1, P, Q0);
+  if constexpr (M == 4) W[2] = fma(-v, Q0, Q2);
+  W[M - 1] = fma(k1, P, -D);
+}
+
 // ---------------------------------------------------------------------------
 // Characteristic-wise WENO-ZA6 (order 2R) flux of the Euler equations at one
 // interface in the sweep-normal frame, from the records of its 2R-point stencil
@@ -447,58 +547,99 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
   // indicators' epsilon is scaled by s^2 (beta and tau scale by s^2) and the
   // descaler's mu_0 by s (mu scales by s), so those two fields take
   // epsilon 4 c^2 eps and mu_0 2 c mu_0 (eq:weight_nonlinear, eq:aimu).
-  T W[M][2 * R], G[M][2 * R];
+  T gh[M];
+  if constexpr (WV == WV_Z1 && sizeof(T) == sizeof(double) && R == 3) {
+    // The projection is linear, so the differences of the characteristic
+    // values between neighbouring stencil points are the projections of the
+    // differences of the states and fluxes between neighbouring cells, and
+    // split_diff needs those and the projected flux of cell i only.  The
+    // FP64 kernels with the paper's Z weights run only for eps <= 1e-40
+    // (larger eps takes the general kernels): there the unscaled eps, an
+    // effective eps / (4 c^2) on the unscaled acoustic fields, moves a
+    // reconstruction by at most ~2e-13 of the stencil's scale.  The stencil
+    // points are read one at a time (a scheduling barrier per pair), which
+    // keeps the raw values of two points live instead of six.
+    T dW[M][5], dG[M][5], gi[M];
+    T pQ0 = ZA_R(Lo::Q0, 0), pQ1 = ZA_R(Lo::Q1, 0), pE = ZA_R(Lo::E, 0);
+    T pQ2 = M == 4 ? ZA_R(M == 4 ? Lo::Q2 : 0, 0) : T(0);
+    T pF1 = ZA_R(Lo::F1, 0), pF3 = ZA_R(Lo::F3, 0);
+    T pF2 = M == 4 ? ZA_R(M == 4 ? Lo::F2 : 0, 0) : T(0);
 #pragma unroll
-  for (int j = 0; j < 2 * R; ++j) {
-    const T Q0 = ZA_R(Lo::Q0, j), Q1 = ZA_R(Lo::Q1, j), E = ZA_R(Lo::E, j);
-    const T Q2 = M == 4 ? ZA_R(M == 4 ? Lo::Q2 : 0, j) : T(0);
-    const T F1 = ZA_R(Lo::F1, j), F3 = ZA_R(Lo::F3, j);
-    const T F2 = M == 4 ? ZA_R(M == 4 ? Lo::F2 : 0, j) : T(0);
-    {
-      T K = fma(u, Q1, -E);
-      if (M == 4) K = fma(v, Q2, K);
-      const T P = fma(q2, Q0, -K);
-      const T D = fma(u, Q0, -Q1);
-      W[0][j] = fma(k1, P, D);
-      W[1][j] = fma(-b1, P, Q0);
-      if (M == 4) W[2][j] = fma(-v, Q0, Q2);
-      W[M - 1][j] = fma(k1, P, -D);
+    for (int k = 0; k < 5; ++k) {
+      const T Q0 = ZA_R(Lo::Q0, k + 1), Q1 = ZA_R(Lo::Q1, k + 1), E = ZA_R(Lo::E, k + 1);
+      const T Q2 = M == 4 ? ZA_R(M == 4 ? Lo::Q2 : 0, k + 1) : T(0);
+      const T F1 = ZA_R(Lo::F1, k + 1), F3 = ZA_R(Lo::F3, k + 1);
+      const T F2 = M == 4 ? ZA_R(M == 4 ? Lo::F2 : 0, k + 1) : T(0);
+      T w[M], g[M];
+      const T dQ1 = Q1 - pQ1;
+      char_project<T, M>(u, v, q2, k1, b1, Q0 - pQ0, dQ1, Q2 - pQ2, E - pE, w);
+      char_project<T, M>(u, v, q2, k1, b1, dQ1, F1 - pF1, F2 - pF2, F3 - pF3, g);
+#pragma unroll
+      for (int f = 0; f < M; ++f) {
+        dW[f][k] = w[f];
+        dG[f][k] = g[f];
+      }
+      if (k + 1 == R - 1) char_project<T, M>(u, v, q2, k1, b1, Q1, F1, F2, F3, gi);
+      pQ0 = Q0; pQ1 = Q1; pQ2 = Q2; pE = E; pF1 = F1; pF2 = F2; pF3 = F3;
+      __builtin_amdgcn_sched_barrier(0);
     }
-    {
-      // physical flux (F0 = Q1, F1, [F2], F3)
-      T K = fma(u, F1, -F3);
-      if (M == 4) K = fma(v, F2, K);
-      const T P = fma(q2, Q1, -K);
-      const T D = fma(u, Q1, -F1);
-      G[0][j] = fma(k1, P, D);
-      G[1][j] = fma(-b1, P, Q1);
-      if (M == 4) G[2][j] = fma(-v, Q1, F2);
-      G[M - 1][j] = fma(k1, P, -D);
+    gh[0] = split_diff(dW[0], dG[0], gi[0], alpha[0], cfg);
+    gh[M - 1] = split_diff(dW[M - 1], dG[M - 1], gi[M - 1], alpha[M - 1], cfg);
+#pragma unroll
+    for (int f = 1; f < M - 1; ++f) gh[f] = split_diff(dW[f], dG[f], gi[f], alpha[f], cfg);
+  } else {
+    T W[M][2 * R], G[M][2 * R];
+#pragma unroll
+    for (int j = 0; j < 2 * R; ++j) {
+      const T Q0 = ZA_R(Lo::Q0, j), Q1 = ZA_R(Lo::Q1, j), E = ZA_R(Lo::E, j);
+      const T Q2 = M == 4 ? ZA_R(M == 4 ? Lo::Q2 : 0, j) : T(0);
+      const T F1 = ZA_R(Lo::F1, j), F3 = ZA_R(Lo::F3, j);
+      const T F2 = M == 4 ? ZA_R(M == 4 ? Lo::F2 : 0, j) : T(0);
+      {
+        T K = fma(u, Q1, -E);
+        if (M == 4) K = fma(v, Q2, K);
+        const T P = fma(q2, Q0, -K);
+        const T D = fma(u, Q0, -Q1);
+        W[0][j] = fma(k1, P, D);
+        W[1][j] = fma(-b1, P, Q0);
+        if (M == 4) W[2][j] = fma(-v, Q0, Q2);
+        W[M - 1][j] = fma(k1, P, -D);
+      }
+      {
+        // physical flux (F0 = Q1, F1, [F2], F3)
+        T K = fma(u, F1, -F3);
+        if (M == 4) K = fma(v, F2, K);
+        const T P = fma(q2, Q1, -K);
+        const T D = fma(u, Q1, -F1);
+        G[0][j] = fma(k1, P, D);
+        G[1][j] = fma(-b1, P, Q1);
+        if (M == 4) G[2][j] = fma(-v, Q1, F2);
+        G[M - 1][j] = fma(k1, P, -D);
+      }
     }
+    // The FP64 kernels with the paper's Z weights run only for eps <= 1e-40
+    // (larger eps takes the general kernels): there the unscaled eps, an
+    // effective eps / (4 c^2) on the unscaled fields, moves a reconstruction
+    // by at most ~2e-13 of the stencil's scale, and the kernels keep the
+    // registers the per-interface eps would take.
+    constexpr bool scale_eps = !(WV == WV_Z1 && sizeof(T) == sizeof(double));
+    WeightCfg<T> cfg_ac = cfg;
+    if (scale_eps) {
+      if (WV == WV_GENERAL && cfg.ai) {
+        cfg_ac.mu0x2 = cfg.mu0x2 * (c + c);
+      } else {
+        const T s2 = T(4) * c2;
+        cfg_ac.eps16 = cfg.eps16 * s2;
+        cfg_ac.eps4 = cfg.eps4 * s2;
+      }
+    }
+    // the two acoustic fields first, so that their epsilon dies early
+    gh[0] = split_pair<T, WV, R>(W[0], G[0], alpha[0], cfg_ac);
+    gh[M - 1] = split_pair<T, WV, R>(W[M - 1], G[M - 1], alpha[M - 1], cfg_ac);
+#pragma unroll
+    for (int s = 1; s < M - 1; ++s) gh[s] = split_pair<T, WV, R>(W[s], G[s], alpha[s], cfg);
   }
 #undef ZA_R
-  // The FP64 kernels with the paper's Z weights run only for eps <= 1e-40
-  // (larger eps takes the general kernels): there the unscaled eps, an
-  // effective eps / (4 c^2) on the unscaled fields, moves a reconstruction
-  // by at most ~2e-13 of the stencil's scale, and the kernels keep the
-  // registers the per-interface eps would take.
-  constexpr bool scale_eps = !(WV == WV_Z1 && sizeof(T) == sizeof(double));
-  WeightCfg<T> cfg_ac = cfg;
-  if (scale_eps) {
-    if (WV == WV_GENERAL && cfg.ai) {
-      cfg_ac.mu0x2 = cfg.mu0x2 * (c + c);
-    } else {
-      const T s2 = T(4) * c2;
-      cfg_ac.eps16 = cfg.eps16 * s2;
-      cfg_ac.eps4 = cfg.eps4 * s2;
-    }
-  }
-  // the two acoustic fields first, so that their epsilon dies early
-  T gh[M];
-  gh[0] = split_pair<T, WV, R>(W[0], G[0], alpha[0], cfg_ac);
-  gh[M - 1] = split_pair<T, WV, R>(W[M - 1], G[M - 1], alpha[M - 1], cfg_ac);
-#pragma unroll
-  for (int s = 1; s < M - 1; ++s) gh[s] = split_pair<T, WV, R>(W[s], G[s], alpha[s], cfg);
   // back-projection F = R g, the acoustic fluxes unscaled by 1/(2c):
   // gh_0 + gh_3 = (gh'_0 + gh'_3)/(2c), c (gh_3 - gh_0) = (gh'_3 - gh'_0)/2
   const T s03 = (gh[0] + gh[M - 1]) * (T(0.5) * ic);

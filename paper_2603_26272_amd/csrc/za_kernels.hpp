@@ -837,7 +837,8 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
     const bool upd = MODE != MODE_FLUX && act && r >= y0 && r < ylast;
     const size_t idx = (size_t)r * nx + x;
     // the x-sweep's part of this row's update, fetched before the fluxes
-    // (LXPRE; otherwise after them, for callers short of registers)
+    // (LXPRE; otherwise right after them, for callers short of registers:
+    // the loads then overlap the synchronisation and the record below)
     double lx[M];
     if (LXPRE && upd) {
 #pragma unroll
@@ -859,6 +860,10 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
 #pragma unroll
         for (int c = 0; c < M; ++c) a.out[(size_t)c * (ny + 1) * nx + (size_t)k * nx + x] = (double)F[c];
       }
+    }
+    if (!LXPRE && upd) {
+#pragma unroll
+      for (int c = 0; c < M; ++c) lx[c] = a.lx[c * cs + idx];
     }
     wave_sync();
     if (need) {
@@ -883,10 +888,6 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
     }
     if (upd) {
       double qnew[M];
-      if (!LXPRE) {
-#pragma unroll
-        for (int c = 0; c < M; ++c) lx[c] = a.lx[c * cs + idx];
-      }
 #pragma unroll
       for (int c = 0; c < M; ++c) {
         const double dF = fw[fk][c][cl] - fw[fkm][c][cl];
@@ -940,7 +941,9 @@ __global__ __launch_bounds__(256) void k_sweep_x_any(SweepArgs a, CfgArg<T> cfg)
 }
 template <int SYS, int M, class T, int MODE, int WV>
 __global__ __launch_bounds__(256, ZA_YS_WAVES) void k_sweep_y(SweepArgs a, CfgArg<T> cfg) {
-  sweep_y_body<SYS, M, T, MODE, WV>(a, cfg, blockIdx.x, blockIdx.y, gridDim.x);
+  // the FP64 Euler flux needs the registers the early x-sweep loads would hold
+  constexpr bool lxpre = !(SYS == SYS_EULER && sizeof(T) == sizeof(double));
+  sweep_y_body<SYS, M, T, MODE, WV, 3, 0, lxpre>(a, cfg, blockIdx.x, blockIdx.y, gridDim.x);
 }
 template <int SYS, int M, class T, int MODE, int WV, int R = 3>
 __global__ __launch_bounds__(256) void k_sweep_y_any(SweepArgs a, CfgArg<T> cfg) {
