@@ -23,7 +23,7 @@ namespace za {
 template <class T>
 struct WeightCfg {
   T eps16;    // 16 epsilon   (Z weights, indicators of 2v scaled by 4)
-  T eps6;     // 6 epsilon    (FP64 Z weights from differences, za6_diff)
+  T eps6;     // 6 epsilon    (Z weights from differences, za6_diff)
   T eps4;     // 4 epsilon    (Ai weights after dividing by mu(2v)^2;
               //               order-2r Z weights on 2v)
   T eps1;     // epsilon      (order-2r Ai weights after dividing by mu(2v)^2)
@@ -135,9 +135,8 @@ __device__ __forceinline__ T z_alpha(T tau, T b, T bmin, const WeightCfg<T>& w) 
 // T/(B + 16 eps) with identical rounding.  (Ai: mu(s) = 2 mu(f) with 2 mu_0,
 // then T/mu(s)^2 and B/mu(s)^2 are 4 tau/mu^2 and 4 beta/mu^2, so 4 eps.)
 //
-// This direct form serves FP32 (three indicators at 16 eps_32 would
-// underflow in a product of weights) and the general weights; the FP64 Z
-// weights take za6_diff below.
+// This direct form serves the general weights and the orders r != 3; the
+// paper's Z weights at r = 3 take za6_diff below.
 // ---------------------------------------------------------------------------
 template <class T, int WV>
 __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const WeightCfg<T>& w) {
@@ -190,7 +189,7 @@ __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const Weigh
 }
 
 // ---------------------------------------------------------------------------
-// FP64 WENO-ZA6 with the paper's Z weights (p = 1, L = q = 1), evaluated from
+// WENO-ZA6 with the paper's Z weights (p = 1, L = q = 1), evaluated from
 // the first differences d_j = s_{j+1} - s_j (j = 0..4) of s = 2 (f_{i-2}, ..,
 // f_{i+3}) and measured from the anchor value s_A (A = 2 or 3): returns
 // 6 (R - s_A), R twice the reconstructed flux as in za6.  Since the weights
@@ -218,7 +217,7 @@ __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const Weigh
 // difference of s (eq:GSI).  Scaling every indicator, tau and eps by the
 // same factor leaves the weights unchanged.
 //
-// Weights over a common denominator,
+// FP64 weights over a common denominator,
 //   R - s_A = sum_k d_k (b_k + T) P_k (q_k - s_A) / sum_k d_k (b_k + T) P_k,
 //   b_k = 6 (beta_k + eps), T = 6 tau, P_k = prod_{j != k} b_j
 //   (the 1/20 of d cancels), (b_k + T) P_k = P + T P_k with P = prod_j b_j,
@@ -227,48 +226,65 @@ __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const Weigh
 // 1e-70 <= eps <= 1e-40, so b_k >= 6e-70 keeps every product above 1e-276
 // and nothing underflows (a smaller eps takes the general kernels); the
 // products overflow only for flux values beyond about 1e37, and the
-// resulting non-finite state is reported.
+// resulting non-finite state is reported.  FP32 takes the normalised
+// weights d_k (1 + T / b_k) with the hardware reciprocal instead: a product
+// of four indicators would underflow at an FP32 epsilon.
 // ---------------------------------------------------------------------------
-template <int A>
-__device__ __forceinline__ double za6_diff(const double (&d)[5], const WeightCfg<double>& w) {
+template <int A, class T>
+__device__ __forceinline__ T za6_diff(const T (&d)[5], const WeightCfg<T>& w) {
   static_assert(A == 2 || A == 3, "anchor s_2 or s_3");
-  const double d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
-  const double d4x2 = d4 + d4;
-  const double kA0 = 2.1556247497997997757, kC0 = 0.59437525020020022427;   // (11 +- sqrt 39)/8
-  const double kA1 = 1.4056247497997997757, kC1 = -0.15562474979979977573;  // (5 +- sqrt 39)/8
-  const double kA3 = 2.0744997998398398206;   // 1.45 + sqrt(39)/10
-  const double kC3 = 2.5877501000800800897;   // 2.9 - sqrt(39)/20
-  const double x0 = fma(kA0, d1, -d0), y0 = fma(kC0, d1, -d0);
-  const double x1 = fma(kA1, d2, -d1), y1 = fma(kC1, d2, -d1);
-  const double x2 = fma(kA0, d2, -d3), y2 = fma(kC0, d2, -d3);
-  const double x3 = fma(kA3, d3, -d4), y3 = fma(kC3, d3, -d4x2);
-  const double b0 = fma(x0, x0, fma(y0, y0, w.eps6));
-  const double b1 = fma(x1, x1, fma(y1, y1, w.eps6));
-  const double b2 = fma(x2, x2, fma(y2, y2, w.eps6));
-  const double bd = fma(x3, x3, fma(y3, y3, w.eps6));
-  const double b3 = 0.25 * ((b0 + b1) + (b2 + bd));   // eq:SI_downwind
-  const double t5 = fma(6.0, d2, fma(-4.0, d1 + d3, d0 + d4));
-  const double tau = (1.5 * t5) * t5;
-  const double p01 = b0 * b1, p23 = b2 * b3;
-  const double P = p01 * p23;
-  const double w0 = fma(tau, b1 * p23, P);
-  const double v1 = fma(tau, b0 * p23, P);   // w_1 / 9
-  const double v2 = fma(tau, p01 * b3, P);   // w_2 / 9
-  const double w3 = fma(tau, p01 * b2, P);
-  // the candidates last: fewer values live across the weights
-  double t0, t1, t2, t3;
-  if (A == 2) {
-    t0 = fma(5.0, d1, -(d0 + d0));
-    t1 = fma(2.0, d2, d1);
-    t2 = fma(4.0, d2, -d3);
-    t3 = fma(6.0, d2, fma(-5.0, d3, d4x2));
+  const T d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
+  const T d4x2 = d4 + d4;
+  const T kA0 = T(2.1556247497997997757), kC0 = T(0.59437525020020022427);   // (11 +- sqrt 39)/8
+  const T kA1 = T(1.4056247497997997757), kC1 = T(-0.15562474979979977573);  // (5 +- sqrt 39)/8
+  const T kA3 = T(2.0744997998398398206);   // 1.45 + sqrt(39)/10
+  const T kC3 = T(2.5877501000800800897);   // 2.9 - sqrt(39)/20
+  const T x0 = fma(kA0, d1, -d0), y0 = fma(kC0, d1, -d0);
+  const T x1 = fma(kA1, d2, -d1), y1 = fma(kC1, d2, -d1);
+  const T x2 = fma(kA0, d2, -d3), y2 = fma(kC0, d2, -d3);
+  const T x3 = fma(kA3, d3, -d4), y3 = fma(kC3, d3, -d4x2);
+  const T b0 = fma(x0, x0, fma(y0, y0, w.eps6));
+  const T b1 = fma(x1, x1, fma(y1, y1, w.eps6));
+  const T b2 = fma(x2, x2, fma(y2, y2, w.eps6));
+  const T bd = fma(x3, x3, fma(y3, y3, w.eps6));
+  const T b3 = T(0.25) * ((b0 + b1) + (b2 + bd));   // eq:SI_downwind
+  const T t5 = fma(T(6), d2, fma(T(-4), d1 + d3, d0 + d4));
+  const T tau = (T(1.5) * t5) * t5;
+  T a0, a1, a2, a3;   // d_k (b_k + T) times a common factor (a1, a2: w_1/9, w_2/9 in FP64)
+  if constexpr (sizeof(T) == sizeof(double)) {
+    const T p01 = b0 * b1, p23 = b2 * b3;
+    const T P = p01 * p23;
+    a0 = fma(tau, b1 * p23, P);
+    a1 = fma(tau, b0 * p23, P);
+    a2 = fma(tau, p01 * b3, P);
+    a3 = fma(tau, p01 * b2, P);
   } else {
-    t0 = fma(-6.0, d2, fma(5.0, d1, -(d0 + d0)));
-    t1 = fma(-4.0, d2, d1);
-    t2 = fma(-2.0, d2, -d3);
-    t3 = fma(-5.0, d3, d4x2);
+    // FP32: normalised weights 1 + tau / b_k with the hardware reciprocal
+    // (a product of four indicators would underflow at the FP32 epsilon)
+    const T tau9 = T(9) * tau;
+    a0 = fma(tau, rcp_nr(b0), T(1));
+    a1 = fma(tau9, rcp_nr(b1), T(9));
+    a2 = fma(tau9, rcp_nr(b2), T(9));
+    a3 = fma(tau, rcp_nr(b3), T(1));
   }
-  return div_nr(fma(w0, t0, fma(9.0, fma(v1, t1, v2 * t2), w3 * t3)), fma(9.0, v1 + v2, w0 + w3));
+  // the candidates last: fewer values live across the weights
+  T t0, t1, t2, t3;
+  if (A == 2) {
+    t0 = fma(T(5), d1, -(d0 + d0));
+    t1 = fma(T(2), d2, d1);
+    t2 = fma(T(4), d2, -d3);
+    t3 = fma(T(6), d2, fma(T(-5), d3, d4x2));
+  } else {
+    t0 = fma(T(-6), d2, fma(T(5), d1, -(d0 + d0)));
+    t1 = fma(T(-4), d2, d1);
+    t2 = fma(T(-2), d2, -d3);
+    t3 = fma(T(-5), d3, d4x2);
+  }
+  if constexpr (sizeof(T) == sizeof(double)) {
+    return div_nr(fma(a0, t0, fma(T(9), fma(a1, t1, a2 * t2), a3 * t3)), fma(T(9), a1 + a2, a0 + a3));
+  } else {
+    return div_nr(fma(a0, t0, fma(a1, t1, fma(a2, t2, a3 * t3))), (a0 + a1) + (a2 + a3));
+  }
 }
 
 // Both Lax-Friedrichs halves of one characteristic field (eq:LF) from the
@@ -278,15 +294,15 @@ __device__ __forceinline__ double za6_diff(const double (&d)[5], const WeightCfg
 // are -(dg - a dw) reversed.  Anchoring the positive half at s^+_2 and the
 // reversed negative half at its fourth value s^-_2 gives
 // F = (R^+ + R^-)/2 = g_2 + (6 (R^+ - s^+_2) + 6 (R^- - s^-_2)) / 12.
-__device__ __forceinline__ double split_diff(const double (&dw)[5], const double (&dg)[5], double g2, double a,
-                                             const WeightCfg<double>& cfg) {
-  double dp[5], dm[5];
+template <class T>
+__device__ __forceinline__ T split_diff(const T (&dw)[5], const T (&dg)[5], T g2, T a, const WeightCfg<T>& cfg) {
+  T dp[5], dm[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     dp[k] = fma(a, dw[k], dg[k]);
     dm[4 - k] = fma(a, dw[k], -dg[k]);
   }
-  return fma(1.0 / 12.0, za6_diff<2>(dp, cfg) + za6_diff<3>(dm, cfg), g2);
+  return fma(T(1.0 / 12.0), za6_diff<2>(dp, cfg) + za6_diff<3>(dm, cfg), g2);
 }
 
 // ---------------------------------------------------------------------------
@@ -381,8 +397,8 @@ __device__ __forceinline__ T zar(const T (&s)[2 * R], const WeightCfg<T>& w) {
 // the reconstruction.
 template <class T, int WV, int R = 3>
 __device__ __forceinline__ T split_pair(const T (&w)[2 * R], const T (&g)[2 * R], T a, const WeightCfg<T>& cfg) {
-  if constexpr (R == 3 && WV == WV_Z1 && sizeof(T) == sizeof(double)) {
-    double dw[5], dg[5];
+  if constexpr (R == 3 && WV == WV_Z1) {
+    T dw[5], dg[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       dw[k] = w[k + 1] - w[k];
@@ -548,7 +564,7 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
   // descaler's mu_0 by s (mu scales by s), so those two fields take
   // epsilon 4 c^2 eps and mu_0 2 c mu_0 (eq:weight_nonlinear, eq:aimu).
   T gh[M];
-  if constexpr (WV == WV_Z1 && sizeof(T) == sizeof(double) && R == 3) {
+  if constexpr (WV == WV_Z1 && R == 3) {
     // The projection is linear, so the differences of the characteristic
     // values between neighbouring stencil points are the projections of the
     // differences of the states and fluxes between neighbouring cells, and
@@ -556,7 +572,8 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
     // FP64 kernels with the paper's Z weights run only for eps <= 1e-40
     // (larger eps takes the general kernels): there the unscaled eps, an
     // effective eps / (4 c^2) on the unscaled acoustic fields, moves a
-    // reconstruction by at most ~2e-13 of the stencil's scale.  The stencil
+    // reconstruction by at most ~2e-13 of the stencil's scale.  FP32 scales
+    // the acoustic fields' epsilon by 4 c^2 exactly as the direct form does.  The stencil
     // points are read one at a time (a scheduling barrier per pair), which
     // keeps the raw values of two points live instead of six.
     T dW[M][5], dG[M][5], gi[M];
@@ -583,8 +600,10 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
       pQ0 = Q0; pQ1 = Q1; pQ2 = Q2; pE = E; pF1 = F1; pF2 = F2; pF3 = F3;
       __builtin_amdgcn_sched_barrier(0);
     }
-    gh[0] = split_diff(dW[0], dG[0], gi[0], alpha[0], cfg);
-    gh[M - 1] = split_diff(dW[M - 1], dG[M - 1], gi[M - 1], alpha[M - 1], cfg);
+    WeightCfg<T> cfg_ac = cfg;
+    if constexpr (sizeof(T) == sizeof(float)) cfg_ac.eps6 = cfg.eps6 * (T(4) * c2);
+    gh[0] = split_diff(dW[0], dG[0], gi[0], alpha[0], cfg_ac);
+    gh[M - 1] = split_diff(dW[M - 1], dG[M - 1], gi[M - 1], alpha[M - 1], cfg_ac);
 #pragma unroll
     for (int f = 1; f < M - 1; ++f) gh[f] = split_diff(dW[f], dG[f], gi[f], alpha[f], cfg);
   } else {
