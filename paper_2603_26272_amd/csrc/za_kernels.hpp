@@ -5,6 +5,17 @@
 
 namespace za {
 
+// Global-memory view of a device pointer.  Every array a sweep reads or
+// writes is device memory; the batched server kernels read their pointers
+// from a table, where the compiler cannot see that and would otherwise use
+// flat memory instructions (64-bit addresses in vector registers, and
+// counted by the LDS wait counter as well, so that a wait for LDS data also
+// waits for those loads).
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 enum Sys { SYS_ADV = 0, SYS_EULER = 1, SYS_BURGERS = 2, SYS_BUCKLEY = 3 };
 enum Mode {
   MODE_FLUX = 0,    // write the interface fluxes
@@ -221,7 +232,7 @@ __device__ __forceinline__ void block_max_store(double (&r)[NPART], double* __re
   if (threadIdx.x < NPART) {
     double v = sm[0][threadIdx.x];
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = wave_max(v, sm[w][threadIdx.x]);
-    dst[threadIdx.x] = v;
+    gptr(dst)[threadIdx.x] = v;
   }
 }
 
@@ -255,16 +266,17 @@ struct NumFields { enum { value = (SYS == SYS_EULER) ? RecLayout<(M == 1 ? 4 : M
 // issue every load before the first record so the latencies overlap.
 template <int SYS, int M, int DIR>
 __device__ __forceinline__ void cell_load(const double* __restrict__ base, size_t cs, size_t off, double (&qd)[M]) {
+  const auto* const b = gptr(base);
   if (SYS == SYS_EULER && M == 4 && DIR == 1) {
-    qd[0] = base[off];
-    qd[1 % M] = base[off + 2 * cs];
-    qd[2 % M] = base[off + cs];
-    qd[3 % M] = base[off + 3 * cs];
+    qd[0] = b[off];
+    qd[1 % M] = b[off + 2 * cs];
+    qd[2 % M] = b[off + cs];
+    qd[3 % M] = b[off + 3 * cs];
   } else if (SYS == SYS_EULER) {
 #pragma unroll
-    for (int c = 0; c < M; ++c) qd[c] = base[off + c * cs];
+    for (int c = 0; c < M; ++c) qd[c] = b[off + c * cs];
   } else {
-    qd[0] = base[off];
+    qd[0] = b[off];
   }
 }
 
@@ -364,7 +376,8 @@ struct SweepConst {
 };
 
 template <int DIR>
-__device__ __forceinline__ SweepConst sweep_const(const DevCtl* ctl, const Geom& g, bool pp, bool two_d) {
+__device__ __forceinline__ SweepConst sweep_const(const DevCtl* ctl_, const Geom& g, bool pp, bool two_d) {
+  const auto* const ctl = gptr(ctl_);
   SweepConst k;
 #pragma unroll
   for (int s = 0; s < 4; ++s) k.al[s] = ctl->alpha[DIR][s];
@@ -463,7 +476,7 @@ __host__ __device__ constexpr int xs_rec(int R) { return (XS_CELLS + 2 * R + 7) 
 template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0>
 __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>& cfg, int bid) {
   constexpr int XS_REC = xs_rec(R);
-  if (a.check_active && !a.ctl->active) return;
+  if (a.check_active && !gptr(a.ctl)->active) return;
   const SweepConst sk = sweep_const<0>(a.ctl, a.g, PP && SYS == SYS_EULER && (MODE == MODE_LX || MODE == MODE_STAGE),
                                        MODE == MODE_LX);
   constexpr int NF = NumFields<SYS, M>::value;
@@ -505,7 +518,7 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
     if (MODE == MODE_FLUX) {
       if (lane < XS_CELLS || k == nx) {
 #pragma unroll
-        for (int c = 0; c < M; ++c) a.out[(size_t)c * ny * (nx + 1) + (size_t)line * (nx + 1) + k] = (double)F[c];
+        for (int c = 0; c < M; ++c) gptr(a.out)[(size_t)c * ny * (nx + 1) + (size_t)line * (nx + 1) + k] = (double)F[c];
       }
     } else {
 #pragma unroll
@@ -532,12 +545,12 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
         } else if (sizeof(T) == sizeof(double)) {
           qc[c] = (double)xr[wv][lane + R];
         } else {
-          qc[c] = a.q[c * cs + idx];
+          qc[c] = gptr(a.q)[c * cs + idx];
         }
       }
       if (a.ca != 0.0) {
 #pragma unroll
-        for (int c = 0; c < M; ++c) qb[c] = a.qn[c * cs + idx];
+        for (int c = 0; c < M; ++c) qb[c] = gptr(a.qn)[c * cs + idx];
       } else {
 #pragma unroll
         for (int c = 0; c < M; ++c) qb[c] = 0.0;
@@ -547,22 +560,22 @@ __device__ __forceinline__ void sweep_x_body(const SweepArgs& a, const CfgArg<T>
       const double kx = -(a.cb * sk.dt) * a.g.inv_dx;
 #pragma unroll
       for (int c = 0; c < M; ++c)
-        a.out[c * cs + idx] = fma(a.ca, qb[c], fma(kx, fl[wv][c][lane + 1] - fl[wv][c][lane], a.cb * qc[c]));
+        gptr(a.out)[c * cs + idx] = fma(a.ca, qb[c], fma(kx, fl[wv][c][lane + 1] - fl[wv][c][lane], a.cb * qc[c]));
     } else {
       double qnew[M], q0[M], qs[M];
       if (MODE == MODE_STAGE) {   // loads first (see the y-sweep epilogue)
 #pragma unroll
-        for (int c = 0; c < M; ++c) { q0[c] = a.qn[c * cs + idx]; qs[c] = a.q[c * cs + idx]; }
+        for (int c = 0; c < M; ++c) { q0[c] = gptr(a.qn)[c * cs + idx]; qs[c] = gptr(a.q)[c * cs + idx]; }
       }
       const double kx = -(a.cb * sk.dt) * a.g.inv_dx;
 #pragma unroll
       for (int c = 0; c < M; ++c) {
         const size_t o = c * cs + idx;
         if (MODE == MODE_RHS) {
-          a.out[o] = -(fl[wv][c][lane + 1] - fl[wv][c][lane]) * a.g.inv_dx;
+          gptr(a.out)[o] = -(fl[wv][c][lane + 1] - fl[wv][c][lane]) * a.g.inv_dx;
         } else {  // MODE_STAGE (1D)
           qnew[c] = fma(a.ca, q0[c], fma(kx, fl[wv][c][lane + 1] - fl[wv][c][lane], a.cb * qs[c]));
-          a.out[o] = qnew[c];
+          gptr(a.out)[o] = qnew[c];
         }
       }
       if (MODE == MODE_STAGE) cell_speeds<SYS, M>(qnew, a.ph, rs);
@@ -602,7 +615,7 @@ static __device__ double xl_sink[4 * 64];
 template <int SYS, int M>
 __device__ __forceinline__ void xl_load(const double* __restrict__ row, size_t cs, int j, double (&qp)[M]) {
 #pragma unroll
-  for (int c = 0; c < M; ++c) qp[c] = row[(size_t)j + c * cs];
+  for (int c = 0; c < M; ++c) qp[c] = gptr(row)[(size_t)j + c * cs];
 }
 
 template <int SYS, int M>
@@ -625,7 +638,7 @@ __device__ __forceinline__ void wave_max_store(double (&r)[NPART], double* __res
   }
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int i = 0; i < NPART; ++i) dst[i] = r[i];
+    for (int i = 0; i < NPART; ++i) gptr(dst)[i] = r[i];
   }
 }
 
@@ -633,7 +646,7 @@ template <int SYS, int M, int WV, int MODE = MODE_LX>
 __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<double>& cfg, int bid) {
   static_assert(MODE == MODE_LX || MODE == MODE_STAGE, "the looped sweep writes stage states");
   constexpr int R = 3;
-  if (a.check_active && !a.ctl->active) return;
+  if (a.check_active && !gptr(a.ctl)->active) return;
   const SweepConst sk = sweep_const<0>(a.ctl, a.g, false, MODE == MODE_LX);
   constexpr int NF = NumFields<SYS, M>::value;
   __shared__ double xr[4][NF * XL_RING];
@@ -680,7 +693,7 @@ __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<d
     for (int c = 0; c < M; ++c) qb[c] = 0.0;
     if (upd && a.ca != 0.0) {
 #pragma unroll
-      for (int c = 0; c < M; ++c) qb[c] = a.qn[c * cs + (size_t)line * nx + i];
+      for (int c = 0; c < M; ++c) qb[c] = gptr(a.qn)[c * cs + (size_t)line * nx + i];
     }
     const int I = I0 + lane;
     double F[M];
@@ -700,7 +713,7 @@ __device__ __forceinline__ void sweep_xl_body(const SweepArgs& a, const CfgArg<d
       // the stores, each chunk issues the same memory operations, and the
       // wait for the next chunk's cells below never waits for these stores.
       const int si = xl_slot(64 * j + lane - 1 + R);
-      double* d = upd ? a.out + (size_t)line * nx + i : xl_sink + lane;
+      auto* d = upd ? gptr(a.out) + (size_t)line * nx + i : gptr(xl_sink) + lane;
       const size_t dstride = upd ? cs : 64;
       double qnew[M];
 #pragma unroll
@@ -831,7 +844,7 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
     if (need) {
       const size_t off = (size_t)bc_map_span(rn, k0 + YS_ROWS + R - 1, YS_ROWS, ny, a.g.bc_y) * nx;
 #pragma unroll
-      for (int c = 0; c < M; ++c) qp[c] = a.q[off + xc + c * cs];
+      for (int c = 0; c < M; ++c) qp[c] = gptr(a.q)[off + xc + c * cs];
     }
     const int r = k - 1;   // cell row finished by this lane
     const bool upd = MODE != MODE_FLUX && act && r >= y0 && r < ylast;
@@ -842,7 +855,7 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
     double lx[M];
     if (LXPRE && upd) {
 #pragma unroll
-      for (int c = 0; c < M; ++c) lx[c] = a.lx[c * cs + idx];
+      for (int c = 0; c < M; ++c) lx[c] = gptr(a.lx)[c * cs + idx];
     }
     if (act) {
       T F[M];
@@ -858,12 +871,12 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
       for (int c = 0; c < M; ++c) fw[fk][c][cl] = (double)F[c];
       if (MODE == MODE_FLUX && (k < kend || k == ny)) {
 #pragma unroll
-        for (int c = 0; c < M; ++c) a.out[(size_t)c * (ny + 1) * nx + (size_t)k * nx + x] = (double)F[c];
+        for (int c = 0; c < M; ++c) gptr(a.out)[(size_t)c * (ny + 1) * nx + (size_t)k * nx + x] = (double)F[c];
       }
     }
     if (!LXPRE && upd) {
 #pragma unroll
-      for (int c = 0; c < M; ++c) lx[c] = a.lx[c * cs + idx];
+      for (int c = 0; c < M; ++c) lx[c] = gptr(a.lx)[c * cs + idx];
     }
     wave_sync();
     if (need) {
@@ -893,10 +906,10 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
         const double dF = fw[fk][c][cl] - fw[fkm][c][cl];
         const size_t o = c * cs + idx;
         if (MODE == MODE_RHS) {
-          a.out[o] = lx[c] - dF * a.g.inv_dy;
+          gptr(a.out)[o] = lx[c] - dF * a.g.inv_dy;
         } else {  // MODE_STAGE: the x-sweep left ca Q^n + cb Q - cb dt dF_x / dx
           qnew[c] = fma(ky, dF, lx[c]);
-          a.out[o] = qnew[c];
+          gptr(a.out)[o] = qnew[c];
         }
       }
       if (MODE == MODE_STAGE) cell_speeds<SYS, M>(qnew, a.ph, rs);
@@ -915,7 +928,7 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
 // band by of the ceil(ny / ytile) bands of (near) equal height.
 template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0, bool LXPRE = true>
 __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>& cfg, int bx, int by, int gx) {
-  if (a.check_active && !a.ctl->active) return;
+  if (a.check_active && !gptr(a.ctl)->active) return;
   const SweepConst sk = sweep_const<1>(a.ctl, a.g, PP && SYS == SYS_EULER && MODE == MODE_STAGE, true);
   double rs[NPART];
 #pragma unroll
