@@ -786,7 +786,7 @@ __device__ __forceinline__ void progress_prio(int st, int nst) {
 // One wavefront's tile: columns x0 .. x0+YS_COLS-1, cell rows [y0, ylast)
 // (interfaces y0 .. ylast).  MODE_STAGE folds the wave speeds of the new
 // states into rs.
-template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0, bool LXPRE = true>
+template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0>
 __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>& cfg, const SweepConst& sk, int x0,
                                              int y0, int ylast, double (&rs)[NPART]) {
   constexpr int YS_RING = ys_ring(R);
@@ -850,10 +850,8 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
     const bool upd = MODE != MODE_FLUX && act && r >= y0 && r < ylast;
     const size_t idx = (size_t)r * nx + x;
     // the x-sweep's part of this row's update, fetched before the fluxes
-    // (LXPRE; otherwise right after them, for callers short of registers:
-    // the loads then overlap the synchronisation and the record below)
     double lx[M];
-    if (LXPRE && upd) {
+    if (upd) {
 #pragma unroll
       for (int c = 0; c < M; ++c) lx[c] = gptr(a.lx)[c * cs + idx];
     }
@@ -873,10 +871,6 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
 #pragma unroll
         for (int c = 0; c < M; ++c) gptr(a.out)[(size_t)c * (ny + 1) * nx + (size_t)k * nx + x] = (double)F[c];
       }
-    }
-    if (!LXPRE && upd) {
-#pragma unroll
-      for (int c = 0; c < M; ++c) lx[c] = gptr(a.lx)[c * cs + idx];
     }
     wave_sync();
     if (need) {
@@ -926,7 +920,7 @@ __device__ __forceinline__ void sweep_y_tile(const SweepArgs& a, const CfgArg<T>
 
 // Block (bx, by) owns 64 columns, one YS_COLS-column tile per wavefront, and
 // band by of the ceil(ny / ytile) bands of (near) equal height.
-template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0, bool LXPRE = true>
+template <int SYS, int M, class T, int MODE, int WV, int R = 3, int PP = 0>
 __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>& cfg, int bx, int by, int gx) {
   if (a.check_active && !gptr(a.ctl)->active) return;
   const SweepConst sk = sweep_const<1>(a.ctl, a.g, PP && SYS == SYS_EULER && MODE == MODE_STAGE, true);
@@ -936,7 +930,7 @@ __device__ __forceinline__ void sweep_y_body(const SweepArgs& a, const CfgArg<T>
   const int ny = a.g.ny;
   const int nb = (ny + a.ytile - 1) / a.ytile;
   const int y0 = (int)((long long)by * ny / nb), ylast = (int)((long long)(by + 1) * ny / nb);
-  sweep_y_tile<SYS, M, T, MODE, WV, R, PP, LXPRE>(a, cfg, sk, bx * 64 + wave_id() * YS_COLS, y0, ylast, rs);
+  sweep_y_tile<SYS, M, T, MODE, WV, R, PP>(a, cfg, sk, bx * 64 + wave_id() * YS_COLS, y0, ylast, rs);
   if (MODE == MODE_STAGE && a.part)
     block_max_store(rs, a.part + ((size_t)by * gx + bx) * NPART);
 }
@@ -954,9 +948,7 @@ __global__ __launch_bounds__(256) void k_sweep_x_any(SweepArgs a, CfgArg<T> cfg)
 }
 template <int SYS, int M, class T, int MODE, int WV>
 __global__ __launch_bounds__(256, ZA_YS_WAVES) void k_sweep_y(SweepArgs a, CfgArg<T> cfg) {
-  // the FP64 Euler flux needs the registers the early x-sweep loads would hold
-  constexpr bool lxpre = !(SYS == SYS_EULER && sizeof(T) == sizeof(double));
-  sweep_y_body<SYS, M, T, MODE, WV, 3, 0, lxpre>(a, cfg, blockIdx.x, blockIdx.y, gridDim.x);
+  sweep_y_body<SYS, M, T, MODE, WV>(a, cfg, blockIdx.x, blockIdx.y, gridDim.x);
 }
 template <int SYS, int M, class T, int MODE, int WV, int R = 3>
 __global__ __launch_bounds__(256) void k_sweep_y_any(SweepArgs a, CfgArg<T> cfg) {

@@ -148,9 +148,8 @@ __global__ __launch_bounds__(256, ZA_YS_WAVES) void kb_sweep_y(const BatchTable*
   const SweepArgs a = slot_args(d, stage, false);
   const CfgArg<T> cfg = slot_cfg<T>(d);
   const int local = b - tab->yoff[s];
-  // FP32 records leave room for the partial stage's early loads; FP64 would spill
-  sweep_y_body<SYS_EULER, 4, T, MODE_STAGE, WV_Z1, 3, 0, sizeof(T) == sizeof(float)>(a, cfg, local % d.ystrips,
-                                                                                    local / d.ystrips, d.ystrips);
+  sweep_y_body<SYS_EULER, 4, T, MODE_STAGE, WV_Z1>(a, cfg, local % d.ystrips,
+                                                   local / d.ystrips, d.ystrips);
 }
 
 __global__ __launch_bounds__(64) void kb_final(const BatchTable* __restrict__ tab, int kind, int dim) {
