@@ -135,8 +135,8 @@ __device__ __forceinline__ T z_alpha(T tau, T b, T bmin, const WeightCfg<T>& w) 
 // T/(B + 16 eps) with identical rounding.  (Ai: mu(s) = 2 mu(f) with 2 mu_0,
 // then T/mu(s)^2 and B/mu(s)^2 are 4 tau/mu^2 and 4 beta/mu^2, so 4 eps.)
 //
-// This direct form serves the general weights and the orders r != 3; the
-// paper's Z weights at r = 3 take za6_diff below.
+// This direct form serves the general weights; the paper's Z weights take
+// za6_diff below (the other orders take zar).
 // ---------------------------------------------------------------------------
 template <class T, int WV>
 __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const WeightCfg<T>& w) {
@@ -394,7 +394,7 @@ __device__ __forceinline__ T zar(const T (&s)[2 * R], const WeightCfg<T>& w) {
 // Both Lax-Friedrichs halves of one characteristic field at one interface
 // (eq:LF): with s^{+-}_j = g_j +- a w_j = 2 f^{+-}_j,
 // F = (R(s^+_{i-r+1..i+r}) + R(s^-_{i+r..i-r+1})) / 2 where R returns twice
-// the reconstruction.
+// the reconstruction (the Z weights at r = 3 from the differences, split_diff).
 template <class T, int WV, int R = 3>
 __device__ __forceinline__ T split_pair(const T (&w)[2 * R], const T (&g)[2 * R], T a, const WeightCfg<T>& cfg) {
   if constexpr (R == 3 && WV == WV_Z1) {
@@ -405,21 +405,22 @@ __device__ __forceinline__ T split_pair(const T (&w)[2 * R], const T (&g)[2 * R]
       dg[k] = g[k + 1] - g[k];
     }
     return split_diff(dw, dg, g[2], a, cfg);
-  }
-  T p[2 * R], m[2 * R];
-#pragma unroll
-  for (int j = 0; j < 2 * R; ++j) {
-    p[j] = fma(a, w[j], g[j]);
-    m[j] = fma(-a, w[j], g[j]);
-  }
-  if constexpr (R == 3) {
-    return T(0.5) * (za6<T, WV>(p[0], p[1], p[2], p[3], p[4], p[5], cfg) +
-                     za6<T, WV>(m[5], m[4], m[3], m[2], m[1], m[0], cfg));
   } else {
-    T mr[2 * R];
+    T p[2 * R], m[2 * R];
 #pragma unroll
-    for (int j = 0; j < 2 * R; ++j) mr[j] = m[2 * R - 1 - j];
-    return T(0.5) * (zar<T, R, WV>(p, cfg) + zar<T, R, WV>(mr, cfg));
+    for (int j = 0; j < 2 * R; ++j) {
+      p[j] = fma(a, w[j], g[j]);
+      m[j] = fma(-a, w[j], g[j]);
+    }
+    if constexpr (R == 3) {
+      return T(0.5) * (za6<T, WV>(p[0], p[1], p[2], p[3], p[4], p[5], cfg) +
+                       za6<T, WV>(m[5], m[4], m[3], m[2], m[1], m[0], cfg));
+    } else {
+      T mr[2 * R];
+#pragma unroll
+      for (int j = 0; j < 2 * R; ++j) mr[j] = m[2 * R - 1 - j];
+      return T(0.5) * (zar<T, R, WV>(p, cfg) + zar<T, R, WV>(mr, cfg));
+    }
   }
 }
 
