@@ -289,20 +289,26 @@ __device__ __forceinline__ T za6_diff(const T (&d)[5], const WeightCfg<T>& w) {
 
 // Both Lax-Friedrichs halves of one characteristic field (eq:LF) from the
 // differences dw, dg of its state and flux values between neighbouring
-// stencil points and its flux value g_2 at x_i: s^{+-} = g +- a w, and the
-// negative half takes its six values in reverse order, whose differences
-// are -(dg - a dw) reversed.  Anchoring the positive half at s^+_2 and the
-// reversed negative half at its fourth value s^-_2 gives
-// F = (R^+ + R^-)/2 = g_2 + (6 (R^+ - s^+_2) + 6 (R^- - s^-_2)) / 12.
+// stencil points: s^{+-} = g +- a w, and the negative half takes its six
+// values in reverse order, whose differences are -(dg - a dw) reversed.
+// Anchoring the positive half at s^+_2 and the reversed negative half at its
+// fourth value s^-_2, with s^+_2 + s^-_2 = 2 g_2, gives
+// F = (R^+ + R^-)/2 = g_2 + S / 12,  S = 6 (R^+ - s^+_2) + 6 (R^- - s^-_2);
+// split_sum returns S.
 template <class T>
-__device__ __forceinline__ T split_diff(const T (&dw)[5], const T (&dg)[5], T g2, T a, const WeightCfg<T>& cfg) {
+__device__ __forceinline__ T split_sum(const T (&dw)[5], const T (&dg)[5], T a, const WeightCfg<T>& cfg) {
   T dp[5], dm[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     dp[k] = fma(a, dw[k], dg[k]);
     dm[4 - k] = fma(a, dw[k], -dg[k]);
   }
-  return fma(T(1.0 / 12.0), za6_diff<2>(dp, cfg) + za6_diff<3>(dm, cfg), g2);
+  return za6_diff<2>(dp, cfg) + za6_diff<3>(dm, cfg);
+}
+
+template <class T>
+__device__ __forceinline__ T split_diff(const T (&dw)[5], const T (&dg)[5], T g2, T a, const WeightCfg<T>& cfg) {
+  return fma(T(1.0 / 12.0), split_sum(dw, dg, a, cfg), g2);
 }
 
 // ---------------------------------------------------------------------------
@@ -564,20 +570,19 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
   // indicators' epsilon is scaled by s^2 (beta and tau scale by s^2) and the
   // descaler's mu_0 by s (mu scales by s), so those two fields take
   // epsilon 4 c^2 eps and mu_0 2 c mu_0 (eq:weight_nonlinear, eq:aimu).
-  T gh[M];
   if constexpr (WV == WV_Z1 && R == 3) {
     // The projection is linear, so the differences of the characteristic
     // values between neighbouring stencil points are the projections of the
     // differences of the states and fluxes between neighbouring cells, and
-    // split_diff needs those and the projected flux of cell i only.  The
-    // FP64 kernels with the paper's Z weights run only for eps <= 1e-40
-    // (larger eps takes the general kernels): there the unscaled eps, an
-    // effective eps / (4 c^2) on the unscaled acoustic fields, moves a
-    // reconstruction by at most ~2e-13 of the stencil's scale.  FP32 scales
-    // the acoustic fields' epsilon by 4 c^2 exactly as the direct form does.  The stencil
-    // points are read one at a time (a scheduling barrier per pair), which
-    // keeps the raw values of two points live instead of six.
-    T dW[M][5], dG[M][5], gi[M];
+    // split_sum needs only those.  The FP64 kernels with the paper's Z
+    // weights run only for eps <= 1e-40 (larger eps takes the general
+    // kernels): there the unscaled eps, an effective eps / (4 c^2) on the
+    // unscaled acoustic fields, moves a reconstruction by at most ~2e-13 of
+    // the stencil's scale.  FP32 scales the acoustic fields' epsilon by
+    // 4 c^2 exactly as the direct form does.  The stencil points are read one
+    // at a time (a scheduling barrier per pair), which keeps the raw values
+    // of two points live instead of six.
+    T dW[M][5], dG[M][5], Fi[4];   // Fi: the physical flux of cell i
     T pQ0 = ZA_R(Lo::Q0, 0), pQ1 = ZA_R(Lo::Q1, 0), pE = ZA_R(Lo::E, 0);
     T pQ2 = M == 4 ? ZA_R(M == 4 ? Lo::Q2 : 0, 0) : T(0);
     T pF1 = ZA_R(Lo::F1, 0), pF3 = ZA_R(Lo::F3, 0);
@@ -597,17 +602,36 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
         dW[f][k] = w[f];
         dG[f][k] = g[f];
       }
-      if (k + 1 == R - 1) char_project<T, M>(u, v, q2, k1, b1, Q1, F1, F2, F3, gi);
+      if (k + 1 == R - 1) { Fi[0] = Q1; Fi[1] = F1; Fi[2] = F2; Fi[3] = F3; }
       pQ0 = Q0; pQ1 = Q1; pQ2 = Q2; pE = E; pF1 = F1; pF2 = F2; pF3 = F3;
       __builtin_amdgcn_sched_barrier(0);
     }
     WeightCfg<T> cfg_ac = cfg;
     if constexpr (sizeof(T) == sizeof(float)) cfg_ac.eps6 = cfg.eps6 * (T(4) * c2);
-    gh[0] = split_diff(dW[0], dG[0], gi[0], alpha[0], cfg_ac);
-    gh[M - 1] = split_diff(dW[M - 1], dG[M - 1], gi[M - 1], alpha[M - 1], cfg_ac);
+    T S[M];
+    S[0] = split_sum(dW[0], dG[0], alpha[0], cfg_ac);
+    S[M - 1] = split_sum(dW[M - 1], dG[M - 1], alpha[M - 1], cfg_ac);
 #pragma unroll
-    for (int f = 1; f < M - 1; ++f) gh[f] = split_diff(dW[f], dG[f], gi[f], alpha[f], cfg);
+    for (int f = 1; f < M - 1; ++f) S[f] = split_sum(dW[f], dG[f], alpha[f], cfg);
+    // F = R (g_i + S / 12) with g_i = L F(Q_i), the projected flux of cell i,
+    // and R L = I: F = F(Q_i) + R S / 12, the back-projection below with the
+    // factor 1/12 folded into its constants and the acoustic fields unscaled
+    // by 1/(2c) as in the direct form.
+    const T k12 = T(1.0 / 12.0);
+    const T s03 = (S[0] + S[M - 1]) * (hc * k12);
+    const T d30 = T(0.5 / 12.0) * (S[M - 1] - S[0]);
+    const T sum = fma(k12, S[1], s03);
+    Fh[0] = Fi[0] + sum;
+    Fh[1] = Fi[1] + fma(u, sum, d30);
+    if constexpr (M == 4) {
+      const T s2 = k12 * S[2];
+      Fh[2] = Fi[2] + fma(v, sum, s2);
+      Fh[3] = Fi[3] + fma(H, s03, fma(u, d30, fma(q2 * k12, S[1], v * s2)));
+    } else {
+      Fh[2] = Fi[3] + fma(H, s03, fma(u, d30, (q2 * k12) * S[1]));
+    }
   } else {
+    T gh[M];
     T W[M][2 * R], G[M][2 * R];
 #pragma unroll
     for (int j = 0; j < 2 * R; ++j) {
@@ -658,21 +682,21 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
     gh[M - 1] = split_pair<T, WV, R>(W[M - 1], G[M - 1], alpha[M - 1], cfg_ac);
 #pragma unroll
     for (int s = 1; s < M - 1; ++s) gh[s] = split_pair<T, WV, R>(W[s], G[s], alpha[s], cfg);
+    // back-projection F = R g, the acoustic fluxes unscaled by 1/(2c):
+    // gh_0 + gh_3 = (gh'_0 + gh'_3)/(2c), c (gh_3 - gh_0) = (gh'_3 - gh'_0)/2
+    const T s03 = (gh[0] + gh[M - 1]) * (T(0.5) * ic);
+    const T d30 = T(0.5) * (gh[M - 1] - gh[0]);
+    const T sum = s03 + gh[1];
+    Fh[0] = sum;
+    Fh[1] = fma(u, sum, d30);
+    if (M == 4) {
+      Fh[2] = fma(v, sum, gh[2]);
+      Fh[3] = fma(H, s03, fma(u, d30, fma(q2, gh[1], v * gh[2])));
+    } else {
+      Fh[2] = fma(H, s03, fma(u, d30, q2 * gh[1]));
+    }
   }
 #undef ZA_R
-  // back-projection F = R g, the acoustic fluxes unscaled by 1/(2c):
-  // gh_0 + gh_3 = (gh'_0 + gh'_3)/(2c), c (gh_3 - gh_0) = (gh'_3 - gh'_0)/2
-  const T s03 = (gh[0] + gh[M - 1]) * (T(0.5) * ic);
-  const T d30 = T(0.5) * (gh[M - 1] - gh[0]);
-  const T sum = s03 + gh[1];
-  Fh[0] = sum;
-  Fh[1] = fma(u, sum, d30);
-  if (M == 4) {
-    Fh[2] = fma(v, sum, gh[2]);
-    Fh[3] = fma(H, s03, fma(u, d30, fma(q2, gh[1], v * gh[2])));
-  } else {
-    Fh[2] = fma(H, s03, fma(u, d30, q2 * gh[1]));
-  }
 }
 
 }  // namespace za
