@@ -24,6 +24,7 @@ template <class T>
 struct WeightCfg {
   T eps16;    // 16 epsilon   (Z weights, indicators of 2v scaled by 4)
   T eps6;     // 6 epsilon    (Z weights from differences, za6_diff)
+  T eps6q;    // 6 epsilon / 4 (its downwind indicator, kept at a quarter)
   T eps4;     // 4 epsilon    (Ai weights after dividing by mu(2v)^2;
               //               order-2r Z weights on 2v)
   T eps1;     // epsilon      (order-2r Ai weights after dividing by mu(2v)^2)
@@ -192,11 +193,11 @@ __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const Weigh
 // WENO-ZA6 with the paper's Z weights (p = 1, L = q = 1), evaluated from
 // the first differences d_j = s_{j+1} - s_j (j = 0..4) of s = 2 (f_{i-2}, ..,
 // f_{i+3}) and measured from the anchor value s_A (A = 2 or 3): returns
-// 6 (R - s_A), R twice the reconstructed flux as in za6.  Since the weights
-// sum to one, R - s_A = sum_k omega_k (q_k - s_A), and 6 (q_k - s_A) has small
-// integer coefficients in the d's:
-//   A = 2:  5 d1 - 2 d0,  d1 + 2 d2,  4 d2 - d3,  6 d2 - 5 d3 + 2 d4
-//   A = 3:  5 d1 - 2 d0 - 6 d2,  d1 - 4 d2,  -2 d2 - d3,  2 d4 - 5 d3
+// 3 (R - s_A), R twice the reconstructed flux as in za6.  Since the weights
+// sum to one, R - s_A = sum_k omega_k (q_k - s_A), and 3 (q_k - s_A) has
+// short coefficients in the d's, one or two FMAs each:
+//   A = 2:  2.5 d1 - d0,  0.5 d1 + d2,  2 d2 - 0.5 d3,  3 d2 - 2.5 d3 + d4
+//   A = 3:  2.5 d1 - d0 - 3 d2,  0.5 d1 - 2 d2,  -d2 - 0.5 d3,  d4 - 2.5 d3
 // (eq:subflux_S6_coeffs written around s_A).
 //
 // Indicators.  With e and g the second differences and twice the slopes of
@@ -209,10 +210,12 @@ __device__ __forceinline__ T za6(T s0, T s1, T s2, T s3, T s4, T s5, const Weigh
 //   k = 0:  x, y = kA0 w - u, kC0 w - u             kA0, kC0 = (11 +- sqrt 39)/8
 //   k = 1:  x, y = kA1 w - u, kC1 w - u             kA1, kC1 = (5 +- sqrt 39)/8
 //   k = 2:  x, y = kA0 u - w, kC0 u - w             (k = 0 mirrored)
-//   k = 3:  x, y = kA3 u - w, kC3 u - 2 w           kA3 = 1.45 + sqrt(39)/10,
-//                                                   kC3 = 2.9 - sqrt(39)/20
+//   k = 3:  x, y = kA3 u - w, kC3 u - w/2           kA3 = (58 - sqrt 39)/40,
+//                                                   kC3 = (29 + 2 sqrt 39)/40
 // (matching the coefficients: kA + kC and kA^2 + kC^2 give the cross and
-// square terms; 2 d4 is shared with the candidates).  Likewise
+// square terms).  The downwind form is kept at a quarter, 2.75 u^2 -
+// 3.625 u w + 1.25 w^2 with eps / 4, so that the average of eq:SI_downwind
+// is one FMA, b_3 = (b_0 + b_1 + b_2) / 4 + b_d / 4.  Likewise
 // 6 tau = 1.5 t5^2 with t5 = d0 - 4 d1 + 6 d2 - 4 d3 + d4 the fifth
 // difference of s (eq:GSI).  Scaling every indicator, tau and eps by the
 // same factor leaves the weights unchanged.
@@ -234,20 +237,20 @@ template <int A, class T>
 __device__ __forceinline__ T za6_diff(const T (&d)[5], const WeightCfg<T>& w) {
   static_assert(A == 2 || A == 3, "anchor s_2 or s_3");
   const T d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
-  const T d4x2 = d4 + d4;
+  const T h4 = T(0.5) * d4;
   const T kA0 = T(2.1556247497997997757), kC0 = T(0.59437525020020022427);   // (11 +- sqrt 39)/8
   const T kA1 = T(1.4056247497997997757), kC1 = T(-0.15562474979979977573);  // (5 +- sqrt 39)/8
-  const T kA3 = T(2.0744997998398398206);   // 1.45 + sqrt(39)/10
-  const T kC3 = T(2.5877501000800800897);   // 2.9 - sqrt(39)/20
+  const T kA3 = T(1.2938750500400400449);   // (58 - sqrt 39)/40
+  const T kC3 = T(1.0372498999199199103);   // (29 + 2 sqrt 39)/40
   const T x0 = fma(kA0, d1, -d0), y0 = fma(kC0, d1, -d0);
   const T x1 = fma(kA1, d2, -d1), y1 = fma(kC1, d2, -d1);
   const T x2 = fma(kA0, d2, -d3), y2 = fma(kC0, d2, -d3);
-  const T x3 = fma(kA3, d3, -d4), y3 = fma(kC3, d3, -d4x2);
+  const T x3 = fma(kA3, d3, -d4), y3 = fma(kC3, d3, -h4);
   const T b0 = fma(x0, x0, fma(y0, y0, w.eps6));
   const T b1 = fma(x1, x1, fma(y1, y1, w.eps6));
   const T b2 = fma(x2, x2, fma(y2, y2, w.eps6));
-  const T bd = fma(x3, x3, fma(y3, y3, w.eps6));
-  const T b3 = T(0.25) * ((b0 + b1) + (b2 + bd));   // eq:SI_downwind
+  const T bq = fma(x3, x3, fma(y3, y3, w.eps6q));    // b_d / 4
+  const T b3 = fma(T(0.25), (b0 + b1) + b2, bq);     // eq:SI_downwind
   const T t5 = fma(T(6), d2, fma(T(-4), d1 + d3, d0 + d4));
   const T tau = (T(1.5) * t5) * t5;
   T a0, a1, a2, a3;   // d_k (b_k + T) times a common factor (a1, a2: w_1/9, w_2/9 in FP64)
@@ -270,15 +273,15 @@ __device__ __forceinline__ T za6_diff(const T (&d)[5], const WeightCfg<T>& w) {
   // the candidates last: fewer values live across the weights
   T t0, t1, t2, t3;
   if (A == 2) {
-    t0 = fma(T(5), d1, -(d0 + d0));
-    t1 = fma(T(2), d2, d1);
-    t2 = fma(T(4), d2, -d3);
-    t3 = fma(T(6), d2, fma(T(-5), d3, d4x2));
+    t0 = fma(T(2.5), d1, -d0);
+    t1 = fma(T(0.5), d1, d2);
+    t2 = fma(T(-0.5), d3, d2 + d2);
+    t3 = fma(T(3), d2, fma(T(-2.5), d3, d4));
   } else {
-    t0 = fma(T(-6), d2, fma(T(5), d1, -(d0 + d0)));
-    t1 = fma(T(-4), d2, d1);
-    t2 = fma(T(-2), d2, -d3);
-    t3 = fma(T(-5), d3, d4x2);
+    t0 = fma(T(2.5), d1, fma(T(-3), d2, -d0));
+    t1 = fma(T(0.5), d1, -(d2 + d2));
+    t2 = fma(T(-0.5), d3, -d2);
+    t3 = fma(T(-2.5), d3, d4);
   }
   if constexpr (sizeof(T) == sizeof(double)) {
     return div_nr(fma(a0, t0, fma(T(9), fma(a1, t1, a2 * t2), a3 * t3)), fma(T(9), a1 + a2, a0 + a3));
@@ -293,7 +296,7 @@ __device__ __forceinline__ T za6_diff(const T (&d)[5], const WeightCfg<T>& w) {
 // values in reverse order, whose differences are -(dg - a dw) reversed.
 // Anchoring the positive half at s^+_2 and the reversed negative half at its
 // fourth value s^-_2, with s^+_2 + s^-_2 = 2 g_2, gives
-// F = (R^+ + R^-)/2 = g_2 + S / 12,  S = 6 (R^+ - s^+_2) + 6 (R^- - s^-_2);
+// F = (R^+ + R^-)/2 = g_2 + S / 6,  S = 3 (R^+ - s^+_2) + 3 (R^- - s^-_2);
 // split_sum returns S.
 template <class T>
 __device__ __forceinline__ T split_sum(const T (&dw)[5], const T (&dg)[5], T a, const WeightCfg<T>& cfg) {
@@ -308,7 +311,7 @@ __device__ __forceinline__ T split_sum(const T (&dw)[5], const T (&dg)[5], T a, 
 
 template <class T>
 __device__ __forceinline__ T split_diff(const T (&dw)[5], const T (&dg)[5], T g2, T a, const WeightCfg<T>& cfg) {
-  return fma(T(1.0 / 12.0), split_sum(dw, dg, a, cfg), g2);
+  return fma(T(1.0 / 6.0), split_sum(dw, dg, a, cfg), g2);
 }
 
 // ---------------------------------------------------------------------------
@@ -607,28 +610,31 @@ __device__ __forceinline__ void euler_flux(const T* __restrict__ rec, int fs, co
       __builtin_amdgcn_sched_barrier(0);
     }
     WeightCfg<T> cfg_ac = cfg;
-    if constexpr (sizeof(T) == sizeof(float)) cfg_ac.eps6 = cfg.eps6 * (T(4) * c2);
+    if constexpr (sizeof(T) == sizeof(float)) {
+      cfg_ac.eps6 = cfg.eps6 * (T(4) * c2);
+      cfg_ac.eps6q = cfg.eps6q * (T(4) * c2);
+    }
     T S[M];
     S[0] = split_sum(dW[0], dG[0], alpha[0], cfg_ac);
     S[M - 1] = split_sum(dW[M - 1], dG[M - 1], alpha[M - 1], cfg_ac);
 #pragma unroll
     for (int f = 1; f < M - 1; ++f) S[f] = split_sum(dW[f], dG[f], alpha[f], cfg);
-    // F = R (g_i + S / 12) with g_i = L F(Q_i), the projected flux of cell i,
-    // and R L = I: F = F(Q_i) + R S / 12, the back-projection below with the
-    // factor 1/12 folded into its constants and the acoustic fields unscaled
+    // F = R (g_i + S / 6) with g_i = L F(Q_i), the projected flux of cell i,
+    // and R L = I: F = F(Q_i) + R S / 6, the back-projection below with the
+    // factor 1/6 folded into its constants and the acoustic fields unscaled
     // by 1/(2c) as in the direct form.
-    const T k12 = T(1.0 / 12.0);
-    const T s03 = (S[0] + S[M - 1]) * (hc * k12);
-    const T d30 = T(0.5 / 12.0) * (S[M - 1] - S[0]);
-    const T sum = fma(k12, S[1], s03);
+    const T k6 = T(1.0 / 6.0);
+    const T s03 = (S[0] + S[M - 1]) * (hc * k6);
+    const T d30 = T(0.5 / 6.0) * (S[M - 1] - S[0]);
+    const T sum = fma(k6, S[1], s03);
     Fh[0] = Fi[0] + sum;
     Fh[1] = Fi[1] + fma(u, sum, d30);
     if constexpr (M == 4) {
-      const T s2 = k12 * S[2];
+      const T s2 = k6 * S[2];
       Fh[2] = Fi[2] + fma(v, sum, s2);
-      Fh[3] = Fi[3] + fma(H, s03, fma(u, d30, fma(q2 * k12, S[1], v * s2)));
+      Fh[3] = Fi[3] + fma(H, s03, fma(u, d30, fma(q2 * k6, S[1], v * s2)));
     } else {
-      Fh[2] = Fi[3] + fma(H, s03, fma(u, d30, (q2 * k12) * S[1]));
+      Fh[2] = Fi[3] + fma(H, s03, fma(u, d30, (q2 * k6) * S[1]));
     }
   } else {
     T gh[M];

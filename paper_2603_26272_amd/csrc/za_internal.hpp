@@ -71,6 +71,7 @@ inline za::CfgArg<T> make_cfg(const za_problem& p) {
   // exact power-of-two rescalings of the reconstruction (see za6() and zar())
   c.w.eps16 = (T)(16.0 * p.eps);
   c.w.eps6 = (T)(6.0 * p.eps);
+  c.w.eps6q = (T)(1.5 * p.eps);
   c.w.eps4 = (T)(4.0 * p.eps);
   c.w.eps1 = (T)p.eps;
   c.w.mu0x2 = (T)(2.0 * p.mu0);

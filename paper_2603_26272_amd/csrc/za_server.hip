@@ -96,7 +96,8 @@ template <class T>
 __device__ __forceinline__ CfgArg<T> slot_cfg(const SlotDesc& d) {
   CfgArg<T> c;
   c.w.eps16 = (T)d.eps16;
-  c.w.eps6 = (T)(0.375 * d.eps16);   // 6 eps, rounded once from the exact 16 eps
+  c.w.eps6 = (T)(0.375 * d.eps16);     // 6 eps, rounded once from the exact 16 eps
+  c.w.eps6q = (T)(0.09375 * d.eps16);  // 1.5 eps, likewise
   c.w.eps4 = (T)d.eps4;
   c.w.mu0x2 = (T)d.mu0x2;
   c.w.p = T(1);

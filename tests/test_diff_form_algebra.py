@@ -9,9 +9,9 @@ What the GPU parity tests check element by element is the kernels'
 arithmetic; this file pins the reading those kernels implement: that
   * each indicator 6 beta_k is x^2 + y^2 of the header's one-FMA forms,
   * 6 tau = 1.5 t5^2 with t5 the fifth difference,
-  * the anchored candidates 6 (q_k - s_A) have the stated integer
-    coefficients for both anchors,
-  * the split flux g_2 + (X^+ + X^-)/12 equals the two halves of eq:LF
+  * the anchored candidates 3 (q_k - s_A) have the stated coefficients for
+    both anchors,
+  * the split flux g_2 + (X^+ + X^-)/6 equals the two halves of eq:LF
     reconstructed by the oracle.
 """
 import os
@@ -37,41 +37,47 @@ def header_constants():
 
 
 def test_constants_are_the_closed_forms():
+    """Each constant is its closed form correctly rounded to FP64 (evaluated
+    in 40-digit decimal arithmetic)."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 40
+    s = Decimal(39).sqrt()
+    want = {"kA0": (11 + s) / 8, "kC0": (11 - s) / 8, "kA1": (5 + s) / 8, "kC1": (5 - s) / 8,
+            "kA3": (58 - s) / 40, "kC3": (29 + 2 * s) / 40}
     k = header_constants()
-    want = {"kA0": (11 + S39) / 8, "kC0": (11 - S39) / 8, "kA1": (5 + S39) / 8, "kC1": (5 - S39) / 8,
-            "kA3": 1.45 + S39 / 10, "kC3": 2.9 - S39 / 20}
     for name, v in want.items():
-        assert k[name] == pytest.approx(v, rel=2e-16, abs=0), name
+        assert k[name] == float(v), name
 
 
 def test_constants_match_the_quadratic_forms():
     """(kA w - u)^2 + (kC w - u)^2 = (kA^2 + kC^2) w^2 - 2 (kA + kC) u w + 2 u^2
     must be 6 beta_k = (3/8)((13/3) e^2 + g^2) in the two differences of the
     stencil: 5 w^2 - 5.5 u w + 2 u^2 (k = 0), 2 w^2 - 2.5 u w + 2 u^2 (k = 1);
-    k = 2 mirrors k = 0; the downwind form (kA3 u - w)^2 + (kC3 u - 2 w)^2
-    must be 11 u^2 - 14.5 u w + 5 w^2."""
+    k = 2 mirrors k = 0; the downwind form (kA3 u - w)^2 + (kC3 u - w/2)^2,
+    kept at a quarter, must be 2.75 u^2 - 3.625 u w + 1.25 w^2."""
     k = header_constants()
     assert k["kA0"] + k["kC0"] == pytest.approx(2.75, rel=1e-15)
     assert k["kA0"] ** 2 + k["kC0"] ** 2 == pytest.approx(5.0, rel=1e-15)
     assert k["kA1"] + k["kC1"] == pytest.approx(1.25, rel=1e-15)
     assert k["kA1"] ** 2 + k["kC1"] ** 2 == pytest.approx(2.0, rel=1e-15)
-    assert k["kA3"] + 2 * k["kC3"] == pytest.approx(7.25, rel=1e-15)
-    assert k["kA3"] ** 2 + k["kC3"] ** 2 == pytest.approx(11.0, rel=1e-15)
+    assert k["kA3"] + 0.5 * k["kC3"] == pytest.approx(1.8125, rel=1e-15)
+    assert k["kA3"] ** 2 + k["kC3"] ** 2 == pytest.approx(2.75, rel=1e-15)
 
 
 def diff_form(d, anchor, eps, k):
-    """6 (R - s_A) from the differences d of s = 2 f, as the kernels form it."""
+    """3 (R - s_A) from the differences d of s = 2 f, as the kernels form it."""
     d0, d1, d2, d3, d4 = d
     x = [k["kA0"] * d1 - d0, k["kA1"] * d2 - d1, k["kA0"] * d2 - d3, k["kA3"] * d3 - d4]
-    y = [k["kC0"] * d1 - d0, k["kC1"] * d2 - d1, k["kC0"] * d2 - d3, k["kC3"] * d3 - 2 * d4]
-    b = [x[i] ** 2 + y[i] ** 2 + 6 * eps for i in range(4)]
-    b[3] = 0.25 * (b[0] + b[1] + b[2] + b[3])
+    y = [k["kC0"] * d1 - d0, k["kC1"] * d2 - d1, k["kC0"] * d2 - d3, k["kC3"] * d3 - 0.5 * d4]
+    b = [x[i] ** 2 + y[i] ** 2 + 6 * eps for i in range(3)]
+    bq = x[3] ** 2 + y[3] ** 2 + 1.5 * eps          # the downwind indicator / 4
+    b.append(0.25 * (b[0] + b[1] + b[2]) + bq)
     t5 = d0 - 4 * d1 + 6 * d2 - 4 * d3 + d4
     tau = 1.5 * t5 * t5
     if anchor == 2:
-        t = [5 * d1 - 2 * d0, d1 + 2 * d2, 4 * d2 - d3, 6 * d2 - 5 * d3 + 2 * d4]
+        t = [2.5 * d1 - d0, 0.5 * d1 + d2, 2 * d2 - 0.5 * d3, 3 * d2 - 2.5 * d3 + d4]
     else:
-        t = [5 * d1 - 2 * d0 - 6 * d2, d1 - 4 * d2, -2 * d2 - d3, 2 * d4 - 5 * d3]
+        t = [2.5 * d1 - d0 - 3 * d2, 0.5 * d1 - 2 * d2, -d2 - 0.5 * d3, d4 - 2.5 * d3]
     a = np.array([1.0, 9.0, 9.0, 1.0]) * (1 + tau / np.array(b))
     return float(a @ np.array(t) / a.sum()), b, tau, t
 
@@ -104,15 +110,15 @@ def test_indicators_tau_and_candidates_against_the_oracle():
         s2, s3 = 2 * f[2], 2 * f[3]
         q = det["q"]
         for i in range(4):
-            assert abs(t[i] / 6 - (2 * q[i] - s2)) <= 1e-13 * np.abs(2 * f).max()
+            assert abs(t[i] / 3 - (2 * q[i] - s2)) <= 1e-13 * np.abs(2 * f).max()
         _, _, _, t3 = diff_form(d, 3, 0.0, k)
         for i in range(4):
-            assert abs(t3[i] / 6 - (2 * q[i] - s3)) <= 1e-13 * np.abs(2 * f).max()
+            assert abs(t3[i] / 3 - (2 * q[i] - s3)) <= 1e-13 * np.abs(2 * f).max()
 
 
 @pytest.mark.parametrize("eps", [1e-40, 1e-6])
 def test_split_flux_equals_the_two_reconstructed_halves(eps):
-    """g_2 + (X^+ + X^-)/12 with the negative half's differences reversed and
+    """g_2 + (X^+ + X^-)/6 with the negative half's differences reversed and
     negated (anchor s^-_2) equals f^+ reconstructed left-biased plus f^-
     reconstructed from the mirrored stencil (eq:LF), both by the oracle."""
     k = header_constants()
@@ -128,7 +134,7 @@ def test_split_flux_equals_the_two_reconstructed_halves(eps):
         dm = (a * dw - dg)[::-1]
         xp, *_ = diff_form(dp, 2, eps, k)
         xm, *_ = diff_form(dm, 3, eps, k)
-        got = f[2] + (xp + xm) / 12
+        got = f[2] + (xp + xm) / 6
         sc = np.abs(fp).max() + np.abs(fm).max()
         worst = max(worst, abs(got - ref) / sc)
     assert worst < 1e-13, worst
