@@ -138,6 +138,25 @@ def test_fluxes_2d_full_size_sampled(dev):
         assert_close(fy[:, :, l], ry[j], 1e-12, f"col {l}")
 
 
+def test_fluxes_2d_full_size_sampled_fp32(dev):
+    """FP32 reconstruction at the full 2048^2 size of the benchmark's FP32
+    leg: 16 rows and 16 columns (both boundaries included) against the
+    oracle's FP32 reading, to the 3e-5 of the small FP32 case."""
+    P, q0 = W.quadrants_2d(0, 2048)
+    P = P.fp32()
+    fx, fy = gpu_fluxes(P, q0, dev)
+    rng = np.random.default_rng(1)
+    lines = sorted(set([0, 1, 2, 1023, 1024, 2045, 2046, 2047] + list(rng.integers(0, 2048, 8))))
+    rx, st = orc.fluxes_lines(P, q0, 0, lines)
+    assert st == 0
+    for j, l in enumerate(lines):
+        assert_close(fx[:, l, :], rx[j], 3e-5, f"fp32 row {l}")
+    ry, st = orc.fluxes_lines(P, q0, 1, lines)
+    assert st == 0
+    for j, l in enumerate(lines):
+        assert_close(fy[:, :, l], ry[j], 3e-5, f"fp32 col {l}")
+
+
 def test_fluxes_2d_advection(dev):
     N = 40
     x = W.centres(N, 0, 1)[None, :]
