@@ -403,6 +403,30 @@ def test_fp32_recon_parity(dev):
     assert_close(fy, ry, 3e-5, "fp32 fy")
 
 
+def test_two_steps_full_size_fp32_against_oracle(dev):
+    """Two RK3 steps of the 2048^2 workload with FP32 reconstruction (the
+    benchmark's FP32 leg), every cell against the oracle's FP32 reading and
+    against its FP64 run.  The flux bar of 3e-5 bounds a stage's update by
+    about 6e-5 of the component scale per direction; the two readings
+    observed 1.0e-7 apart (2.8e-8 from FP64), and both bars here are 1e-6.
+    The second step's dt follows the FP32-rounded states, so the times agree
+    to 1e-7 relative rather than bit for bit."""
+    P64, q0 = W.quadrants_2d(0, 2048)
+    P = P64.fp32()
+    q = torch.from_numpy(q0).to(dev)
+    with Ctx(P) as ctx:
+        info = ctx.solve(q, 0.0, 2)
+    got = q.cpu().numpy()
+    orc.set_threads(16)
+    ref, steps, t, st = orc.solve(P, q0, 0.0, 2)
+    assert st == 0 and steps == 2 and info["steps"] == 2
+    assert abs(info["t"] - t) <= 1e-7 * t
+    assert_close(got, ref, 1e-6, "fp32 2048^2, two steps")
+    ref64, steps, t64, st = orc.solve(P64, q0, 0.0, 2)
+    assert st == 0 and steps == 2
+    assert_close(got, ref64, 1e-6, "fp32 2048^2 against the FP64 oracle")
+
+
 def test_determinism_bitwise(dev):
     P, q0 = W.quadrants_2d(8, 128, 128)
     outs = []
