@@ -3,7 +3,8 @@ quadrants at 4096^2 (four times the benchmark grid; sampled fluxes and one
 full RK3 step in the stage kernels' launch configuration) and a 1D Euler
 line of 2^20 + 3 cells (every flux), against the oracle; and a 33000^2 grid
 (half the library's 2^31-cell limit, past 32-bit offsets) that tiles a
-periodic 3000^2 one, bitwise against the small grid's results."""
+periodic 3000^2 one and a 1D line of 1.09998e9 cells that tiles a periodic
+line of 999983, bitwise against the small grids' results."""
 import numpy as np
 import pytest
 
@@ -134,6 +135,57 @@ def test_tiled_grid_past_32_bit_offsets_bitwise(dev):
         assert dtb == dts
         bad = _tiles_equal(qb, qs, k, nt)
         assert bad is None, "stepped state: " + bad
+    finally:
+        del qb
+        torch.cuda.empty_cache()
+
+
+def test_tiled_line_past_32_bit_offsets_bitwise(dev):
+    """A 1D Euler line of 1.09998e9 cells tiling a periodic line of 999983
+    cells 1100 times (the same mesh width): byte offsets pass 2^32 within the
+    first component and element offsets pass 2^31 in the second, through the
+    1D paths (the looped stage sweep with its maxima rows per wavefront, the
+    one-shot flux sweep).  Fluxes, the CFL step and the stepped state equal
+    the short line's, tiled, bit for bit; the short line's step is checked
+    against the oracle."""
+    nt, k = 999983, 1100
+    n = nt * k
+    free, _ = torch.cuda.mem_get_info()
+    need = 4 * 3 * n * 8 + (4 << 30)   # state, two context states, the fluxes
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory, {free / 2**30:.0f} GiB free")
+    from paper_2603_26272_amd.problem import EULER, PERIODIC, Problem
+    x = W.centres(nt, 0.0, 1.0)
+    rho = 1.0 + 0.3 * np.sin(6 * np.pi * x) + 0.5 * (x > 0.4)
+    u = 0.4 * np.sin(2 * np.pi * x) + 0.1 * np.cos(10 * np.pi * x)
+    p = 1.0 + 0.2 * np.cos(10 * np.pi * x) + 0.4 * (x > 0.7)
+    q_t = np.ascontiguousarray(W.conservative(rho, u, 0.0, p, dim=1).reshape(3, 1, nt))
+    Pt = Problem(dim=1, system=EULER, nx=nt, bc_x=PERIODIC, cfl=0.5)
+    Pb = Pt.with_(nx=n, xhi=float(k))
+    assert Pb.dx == Pt.dx
+
+    qs = torch.from_numpy(q_t).to(dev)
+    with Ctx(Pt) as ctx:
+        fs, _ = ctx.rhs_fluxes(qs)
+        dts = ctx.step(qs, 0.0, sync=True)
+    torch.cuda.synchronize()
+    assert dts == orc.cfl_dt(Pt, q_t)
+    ref, steps, t, st = orc.solve(Pt, q_t, 0.0, 1)
+    assert st == 0 and steps == 1 and t == dts
+    assert_close(qs.cpu().numpy(), ref, 1e-10, "periodic line of 999983 cells, one step")
+
+    qb = torch.from_numpy(q_t).to(dev).repeat(1, 1, k)
+    try:
+        with Ctx(Pb) as ctx:
+            fb, _ = ctx.rhs_fluxes(qb)
+            torch.cuda.synchronize()
+            assert bool((fb[:, 0, :n].view(3, k, nt) == fs[:, 0, :nt].view(3, 1, nt)).all()), "fluxes"
+            assert torch.equal(fb[:, 0, n], fs[:, 0, nt]), "last interface"
+            del fb
+            dtb = ctx.step(qb, 0.0, sync=True)
+        torch.cuda.synchronize()
+        assert dtb == dts
+        assert bool((qb.view(3, k, nt) == qs.view(3, 1, nt)).all()), "stepped state"
     finally:
         del qb
         torch.cuda.empty_cache()
