@@ -82,7 +82,8 @@ def _tiles_equal(big, small, k, nt):
     return None
 
 
-def test_tiled_grid_past_32_bit_offsets_bitwise(dev):
+@pytest.mark.parametrize("fp32", [False, True])
+def test_tiled_grid_past_32_bit_offsets_bitwise(dev, fp32):
     """33000^2 = 1.089e9 cells: the state's byte offsets pass 2^32 in its
     first component and its element offsets pass 2^31 in the second, so a
     32-bit index product anywhere in the sweeps or the stage updates would
@@ -92,7 +93,11 @@ def test_tiled_grid_past_32_bit_offsets_bitwise(dev):
     sees the stencil values of its image in the small grid, and the global
     wave speeds are maxima over the same values, so the interface fluxes,
     the CFL step and the stepped state must equal the small grid's, tiled,
-    bit for bit.  The small grid's step is checked against the oracle."""
+    bit for bit.  The small grid's step is checked against the oracle (FP32
+    reconstruction, whose stage sweeps are the one-shot kernels: against
+    its FP32 reading, to the 1e-4 of the component scale that the flux bar
+    of 3e-5 allows a step; the two readings differ by up to 8.2e-6 at this
+    data's sharpest points)."""
     nt, k = 3000, 11
     n = nt * k
     free, _ = torch.cuda.mem_get_info()
@@ -108,6 +113,8 @@ def test_tiled_grid_past_32_bit_offsets_bitwise(dev):
     p = 1.0 + 0.2 * np.cos(2 * np.pi * (x - 2 * y)) + 0.4 * (x + y > 1.0)
     q_t = np.ascontiguousarray(W.conservative(rho, u, v, p, dim=2))
     Pt = Problem(dim=2, system=EULER, nx=nt, ny=nt, bc_x=PERIODIC, bc_y=PERIODIC, cfl=0.5)
+    if fp32:
+        Pt = Pt.fp32()
     Pb = Pt.with_(nx=n, ny=n, xhi=float(k), yhi=float(k))
     assert Pb.dx == Pt.dx and Pb.dy == Pt.dy
 
@@ -120,7 +127,7 @@ def test_tiled_grid_past_32_bit_offsets_bitwise(dev):
     assert dts == orc.cfl_dt(Pt, q_t)
     ref, steps, t, st = orc.solve(Pt, q_t, 0.0, 1)
     assert st == 0 and steps == 1 and t == dts
-    assert_close(qs.cpu().numpy(), ref, 1e-10, "3000^2 periodic, one step")
+    assert_close(qs.cpu().numpy(), ref, 1e-4 if fp32 else 1e-10, "3000^2 periodic, one step")
 
     qb = torch.from_numpy(q_t).to(dev).repeat(1, k, k)
     try:

@@ -464,7 +464,7 @@ def test_nonfinite_reported(dev):
 def test_invalid_arguments(dev):
     from paper_2603_26272_amd.za import ZA_ERR_ARG, ZaError
     for bad in (Problem(dim=3), Problem(nx=0), Problem(dim=1, ny=4), Problem(cfl=-1.0), Problem(p=0.5),
-                Problem(precision=1, eps=1e-40)):
+                Problem(precision=1, eps=1e-40), Problem(dim=2, nx=1 << 16, ny=(1 << 15) + 1)):
         with pytest.raises(ZaError) as ei:
             Ctx(bad)
         assert ei.value.status == ZA_ERR_ARG
